@@ -1,0 +1,220 @@
+/*
+ * nacrith.h -- C ABI of the MI355X (gfx950) per-token probability pipeline of the Nacrith
+ * neural lossless text compressor (arXiv 2602.19626).
+ *
+ * The pipeline, per token of each stream (paper Algorithm 1):
+ *   135M-shape decoder-only transformer forward over a sliding KV cache (sections 3.2, 3.10)
+ *   -> vocabulary softmax (section 3.3) -> adaptive log-space bias head (section 3.7)
+ *   -> token n-gram and confidence skip (sections 3.5, 3.8) -> linear mixer (section 3.6)
+ *   -> CDF-24 quantisation (section 3.4) -> 32-bit arithmetic coder on the host (section 3.9).
+ *
+ * Conventions for every call:
+ *  - Return value: NC_OK or an nc_status error; nc_last_error() gives a thread-local message.
+ *    No C++ exception crosses this interface.
+ *  - Buffers: the caller owns every input and output buffer.  Pointers documented as "host" are
+ *    ordinary host memory; pointers documented as "device" are HIP device allocations on the
+ *    context's device (for example torch tensors on cuda:0); `stream` arguments are hipStream_t
+ *    values passed as void* (NULL = the default stream).  The library owns the context and all
+ *    device state it allocates.
+ *  - A context is used by one host thread at a time.
+ *  - Token ids are int32 in [0, vocab).  Probabilities are float32.  CDFs are uint32 with
+ *    vocab + 1 entries, cdf[0] = 0 and cdf[vocab] = total.
+ */
+#ifndef NACRITH_H
+#define NACRITH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nc_status {
+  NC_OK = 0,
+  NC_E_INVALID = 1,   /* bad argument: token out of range, NaN/negative probability, bad shape */
+  NC_E_DEVICE = 2,    /* a HIP runtime call failed */
+  NC_E_NOMEM = 3,     /* a device or host allocation failed */
+  NC_E_CAPACITY = 4,  /* an output buffer is too small; the required size is reported */
+  NC_E_CORRUPT = 5,   /* the decoder consumed more than 8 * bytes + 32 bits */
+  NC_E_STATE = 6      /* call sequence violates the context state (e.g. history mismatch) */
+} nc_status;
+
+enum { NC_FP32 = 0, NC_BF16 = 1, NC_FP8 = 2 };                 /* GEMM operand precision */
+enum { NC_SKIP_NONE = 0, NC_SKIP_ENTROPY = 1, NC_SKIP_PMAX = 2 };  /* section 3.8 skip rule */
+enum {
+  NC_F_HEAD = 1u << 0,      /* adaptive bias head, section 3.7 */
+  NC_F_NGRAM = 1u << 1,     /* token n-gram, section 3.5 */
+  NC_F_SKIP = 1u << 2,      /* confidence-based LLM skip, section 3.8 */
+  NC_F_MIXER = 1u << 3,     /* linear context mixer, section 3.6 */
+  NC_F_ENSEMBLE = 1u << 4   /* softmax-gated {LLM, n-gram orders 1..K} head trained by SGD */
+};
+enum { NC_MODE_LLM = 0, NC_MODE_SKIP = 1, NC_MODE_MIX = 2, NC_MODE_ENSEMBLE = 3 };
+
+/* Model shape, ensemble constants and run options.  All fields are read at nc_create(). */
+typedef struct nc_config {
+  int32_t n_layers, d_model, n_heads, n_kv_heads, head_dim, d_ffn, vocab;
+  float rope_theta;          /* RoPE base; rotate-half pairs (i, i + head_dim/2) */
+  float norm_eps;            /* RMSNorm epsilon */
+  int32_t ctx_len;           /* L: KV entries kept (section 3.10); multiple of slide */
+  int32_t slide;             /* C: entries dropped when appending to a full cache */
+  int32_t ngram_order;       /* K: orders 1..K (section 3.5), 1 <= K <= 4 */
+  float ngram_eps;           /* lambda_k = n_k / (n_k + eps), eps = 5 in the paper */
+  int32_t ngram_max_contexts;/* per order; no new context is stored once reached (500,000) */
+  float head_lr;             /* alpha of the bias head, 1e-3 (section 3.7); also the SGD lr
+                                of the ensemble gate */
+  float mix_eta;             /* exponential-weights rate of the mixer (section 3.6) */
+  float mix_w_llm;           /* initial LLM weight of the two-model mixer (0.85; 0.5 uniform) */
+  int32_t warmup;            /* tokens coded by the LLM alone before skip/mix (100) */
+  int32_t skip_mode;         /* NC_SKIP_* */
+  float skip_entropy_bits;   /* skip when H(p_ngram) < this (1.5 bits) */
+  float skip_pmax;           /* skip when max p_ngram >= this (0.99) */
+  uint32_t cdf_total;        /* T, 2^24 (section 3.4); vocab < T <= 2^24 */
+  int32_t precision;         /* NC_FP32 | NC_BF16 | NC_FP8 */
+  uint32_t features;         /* NC_F_* bit set */
+  int32_t max_streams;       /* streams that can be coded together by one call */
+} nc_config;
+
+/* Optional diagnostics of nc_probs_for_context(); every array pointer may be NULL. */
+typedef struct nc_probe {
+  float* logits;             /* host, vocab floats: LLM logits z (valid if llm_ran) */
+  float* ptilde;             /* host, vocab floats: bias-head output softmax(z + b) */
+  float* p_ngram;            /* host, vocab floats: n-gram distribution P_K */
+  uint32_t* cdf;             /* host, vocab + 1 uint32: the CDF-24 of the coding distribution */
+  int32_t mode;              /* out: NC_MODE_* used at this position */
+  int32_t llm_ran;           /* out: 1 if the transformer produced logits for this position */
+  float entropy_bits;        /* out: H(p_ngram) in bits */
+  float pmax;                /* out: max p_ngram */
+  float mix_w[2];            /* out: mixer weights before this position's update */
+} nc_probe;
+
+/* Per-call statistics of the last encode/decode on a context. */
+typedef struct nc_stats {
+  uint64_t tokens;           /* tokens coded */
+  uint64_t llm_rows;         /* positions whose logits were used (not skipped) */
+  uint64_t skipped;          /* positions coded by the n-gram alone */
+  uint64_t body_rows;        /* transformer rows evaluated (KV appends) */
+  double bits;               /* exact coded bits (sum over streams) */
+  double ideal_bits;         /* sum -log2 p_i(t_i) of the float32 coding distributions */
+  double seconds;            /* wall time of the call */
+} nc_stats;
+
+typedef struct nc_ctx nc_ctx;
+
+/* ---- lifecycle ----------------------------------------------------------------------------- */
+
+/* Create a context on the current HIP device.  weights_f32 (host) is the flat float32 buffer:
+ * E[vocab][d], then per layer attn_norm[d], Wq[Hq*hd][d], Wk[Hkv*hd][d], Wv[Hkv*hd][d],
+ * Wo[d][Hq*hd], mlp_norm[d], Wg[ffn][d], Wu[ffn][d], Wd[d][ffn], then final_norm[d]
+ * (matrices [out][in], y = x W^T; E is tied as the output matrix, section 3.2 Eq. (lm) with no
+ * output bias).  It is copied; the caller may free it on return.  The precision copies (BF16,
+ * FP8 with per-tensor scales) are made on the device.  Errors: NC_E_INVALID (shape, NULL),
+ * NC_E_NOMEM, NC_E_DEVICE. */
+nc_status nc_create(const nc_config* cfg, const float* weights_f32, nc_ctx** out);
+
+/* Release a context and all its device memory.  NULL-safe. */
+void nc_destroy(nc_ctx* ctx);
+
+/* Reset (and size) the per-stream state for n_streams streams of up to max_tokens tokens each:
+ * KV caches, n-gram tables, bias vectors, mixer weights and histories are cleared
+ * (Algorithm 1 "Initialize").  NC_E_INVALID if n_streams > cfg.max_streams. */
+nc_status nc_streams_reset(nc_ctx* ctx, uint32_t n_streams, uint32_t max_tokens);
+
+/* Static FP8 activation scales (per-tensor amax / 448), calibrated by running the FP32 model
+ * on tokens[0..n) of a calibration stream.  Required once before FP8 coding. */
+nc_status nc_calibrate_fp8(nc_ctx* ctx, const int32_t* tokens, size_t n);
+
+/* ---- the pipeline ------------------------------------------------------------------------ */
+
+/* Coding distribution for position n of `stream` given its history tokens[0..n) (host)
+ * (Algorithm 1, the steps before probs_to_cdf).  Tokens beyond those already committed on this
+ * stream are committed first, exactly as the encoder would (each one updates the head, mixer and
+ * n-gram).  NC_E_STATE if tokens[0..committed) differs from the committed history.
+ * probs (host) receives vocab floats; probe may be NULL. */
+nc_status nc_probs_for_context(nc_ctx* ctx, uint32_t stream, const int32_t* tokens, size_t n,
+                               float* probs, nc_probe* probe);
+
+/* Algorithm 1 "Update: N-gram, Mixer, AdaptiveHead with t_i": commit `token` as the next token
+ * of `stream`, using the distribution of the last nc_probs_for_context() at that position
+ * (computed on demand if there was none). */
+nc_status nc_mix_update(nc_ctx* ctx, uint32_t stream, int32_t token);
+
+/* CDF-24 quantisation, section 3.4 (Algorithm 1 probs_to_cdf(p, 2^24)): for each of `rows`
+ * rows, c_i = max(1, floor(p_i (total - vocab))) computed exactly from the float32 value, the
+ * residual total - sum(c) added to the lowest-index argmax, cdf = exclusive prefix sum.
+ * probs: device, rows x vocab float32 (row-major).  cdf: device, rows x (vocab + 1) uint32.
+ * row_status: device, rows int32 (0 ok, 1 = NaN/negative/>1 probability or mass above total,
+ * in which case that row's cdf is unspecified); may be NULL.  Pure: no context needed.
+ * Errors: NC_E_INVALID for vocab outside [1, 262144], total <= vocab, total > 2^24, NULL
+ * pointers.  Uses a library-owned device workspace (rows * ceil(vocab/4096) * 16 bytes). */
+nc_status nc_quantize_cdf24(const float* probs, uint32_t rows, uint32_t vocab, uint32_t total,
+                            uint32_t* cdf, int32_t* row_status, void* stream);
+
+/* Interval lookup on CDF rows (section 3.9): mode 0 (encode) key[r] is a symbol s and the
+ * output is (s, cdf[s], cdf[s+1]); mode 1 (decode) key[r] is a target count and the output is
+ * the largest s with cdf[s] <= target, with its interval.  cdf: device rows x (vocab+1);
+ * key: device rows uint32; out: device rows x 3 uint32. */
+nc_status nc_cdf_interval(const uint32_t* cdf, uint32_t rows, uint32_t vocab,
+                          const uint32_t* key, int32_t mode, uint32_t* out, void* stream);
+
+/* Worst-case bytes of one encoded stream of n_tokens tokens: ceil((25 n + 64) / 8). */
+size_t nc_encode_bound(size_t n_tokens);
+
+/* Compress n_streams independent streams (Algorithm 1 + ArithEncoder.finish), batched on the
+ * GPU.  tokens[s] (host) has n_tokens[s] ids; out[s] (host) has out_cap[s] bytes; on return
+ * out_bytes[s] and out_bits[s] give the exact code size (bits packed MSB-first, last byte
+ * zero-padded).  Resets the stream state first.  NC_E_CAPACITY if out_cap[s] <
+ * nc_encode_bound(n_tokens[s]) (out_bytes[s] then holds that bound). */
+nc_status nc_encode_stream(nc_ctx* ctx, uint32_t n_streams, const int32_t* const* tokens,
+                           const size_t* n_tokens, uint8_t* const* out, const size_t* out_cap,
+                           size_t* out_bytes, uint64_t* out_bits);
+
+/* Decompress (the mirror of encode, section 3.1): in[s] (host, in_bytes[s] bytes) holds
+ * n_tokens[s] tokens, which are written to tokens_out[s] (host).  NC_E_CORRUPT if a decoder
+ * reads past 8 * in_bytes[s] + 32 bits. */
+nc_status nc_decode_stream(nc_ctx* ctx, uint32_t n_streams, const uint8_t* const* in,
+                           const size_t* in_bytes, const size_t* n_tokens,
+                           int32_t* const* tokens_out);
+
+/* Statistics of the last nc_encode_stream / nc_decode_stream call. */
+nc_status nc_get_stats(const nc_ctx* ctx, nc_stats* out);
+
+/* ---- host arithmetic coder (section 3.9), exposed for testing and container tools --------- */
+
+/* Encode n intervals (host, n x 2 uint32: cl, ch with 0 <= cl < ch <= total) with the 32-bit
+ * coder.  out (host) has cap bytes; NC_E_CAPACITY if too small (out_bytes = needed bound). */
+nc_status nc_ac_encode(const uint32_t* intervals, size_t n, uint32_t total, uint8_t* out,
+                       size_t cap, size_t* out_bytes, uint64_t* out_bits);
+
+/* Decode n symbols that were all coded against the same CDF (host, vocab + 1 uint32). */
+nc_status nc_ac_decode_static(const uint8_t* in, size_t in_bytes, const uint32_t* cdf,
+                              uint32_t vocab, size_t n, int32_t* out);
+
+/* ---- softmax-gated ensemble head (differentiation workload) ------------------------------ */
+
+/* Forward of the ensemble head for `rows` rows: q0 = softmax(z + b), w = softmax(theta),
+ * p = w_0 q0 + sum_{j>=1} w_j P_j, loss[r] = -log p(t*_r).  All device pointers:
+ * z rows x vocab, b vocab, theta n_experts, P rows x (n_experts-1) x vocab, target rows int32;
+ * outputs loss rows, p rows x vocab (may be NULL), resp rows x n_experts (responsibilities
+ * r_j = w_j q_j(t*) / p(t*), needed by the backward).  n_experts <= 8. */
+nc_status nc_ensemble_forward(const float* z, const float* b, const float* theta,
+                              const float* P, const int32_t* target, uint32_t rows,
+                              uint32_t vocab, uint32_t n_experts, float* loss, float* p,
+                              float* resp, void* stream);
+
+/* Backward: grad_b[t] = sum_r g_r r_{r,0} (q0_r(t) - 1[t = t*_r]),
+ * grad_theta[j] = sum_r g_r (w_j - r_{r,j}), with g = grad_loss (device, rows) -- a fixed-order
+ * reduction over rows (no float atomics).  If lr != 0 the SGD step b -= lr grad_b,
+ * theta -= lr grad_theta is applied in place as well (b, theta writable device pointers). */
+nc_status nc_ensemble_backward(const float* z, float* b, float* theta, const float* resp,
+                               const int32_t* target, const float* grad_loss, uint32_t rows,
+                               uint32_t vocab, uint32_t n_experts, float lr, float* grad_b,
+                               float* grad_theta, void* stream);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char* nc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NACRITH_H */

@@ -1,0 +1,114 @@
+// extern "C" entry points of libnacrith: argument checking and error translation only; the work
+// happens in the kernels (k_*.hip), the host coder (coder.cpp) and the runtime (runtime.cpp).
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "coder.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace nc {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// Device workspace of the context-free calls, one growing buffer per device.  hipFree of a
+// smaller old buffer synchronises the device, so work still using it has finished.
+static void* pure_call_workspace(size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_map<int, std::pair<void*, size_t>> bufs;
+  int dev = 0;
+  NC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto& b = bufs[dev];
+  if (b.second < bytes) {
+    if (b.first) NC_HIP(hipFree(b.first));
+    b.first = nullptr;
+    b.second = 0;
+    NC_HIP(hipMalloc(&b.first, bytes));
+    b.second = bytes;
+  }
+  return b.first;
+}
+}  // namespace nc
+
+using namespace nc;
+
+extern "C" {
+
+const char* nc_last_error(void) { return g_last_error.c_str(); }
+
+size_t nc_encode_bound(size_t n_tokens) { return encode_bound(n_tokens); }
+
+nc_status nc_quantize_cdf24(const float* probs, uint32_t rows, uint32_t vocab, uint32_t total,
+                            uint32_t* cdf, int32_t* row_status, void* stream) {
+  return guard([&] {
+    NC_CHECK(probs && cdf, NC_E_INVALID, "NULL pointer");
+    NC_CHECK(vocab >= 1 && vocab <= 262144u, NC_E_INVALID, "vocab must be in [1, 262144]");
+    NC_CHECK(total > vocab && total <= (1u << 24), NC_E_INVALID,
+             "total must satisfy vocab < total <= 2^24");
+    if (rows == 0) return;
+    void* ws = pure_call_workspace(quantize_workspace_bytes(rows, vocab));
+    launch_quantize_cdf(probs, rows, vocab, total, cdf, row_status, ws,
+                        static_cast<hipStream_t>(stream));
+  });
+}
+
+nc_status nc_cdf_interval(const uint32_t* cdf, uint32_t rows, uint32_t vocab, const uint32_t* key,
+                          int32_t mode, uint32_t* out, void* stream) {
+  return guard([&] {
+    NC_CHECK(cdf && key && out, NC_E_INVALID, "NULL pointer");
+    NC_CHECK(vocab >= 1, NC_E_INVALID, "vocab must be >= 1");
+    NC_CHECK(mode == 0 || mode == 1, NC_E_INVALID, "mode must be 0 (encode) or 1 (decode)");
+    launch_cdf_interval(cdf, rows, vocab, key, mode, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+nc_status nc_ac_encode(const uint32_t* intervals, size_t n, uint32_t total, uint8_t* out,
+                       size_t cap, size_t* out_bytes, uint64_t* out_bits) {
+  return guard([&] {
+    NC_CHECK(out_bytes && out_bits && (n == 0 || intervals), NC_E_INVALID, "NULL pointer");
+    NC_CHECK(total >= 2 && total <= (1u << 24), NC_E_INVALID, "total must be in [2, 2^24]");
+    for (size_t i = 0; i < n; ++i)
+      NC_CHECK(intervals[2 * i] < intervals[2 * i + 1] && intervals[2 * i + 1] <= total,
+               NC_E_INVALID, "interval %zu is empty or out of range", i);
+    std::vector<uint8_t> buf;
+    buf.reserve(encode_bound(n));
+    ArithEncoder enc(&buf, total);
+    for (size_t i = 0; i < n; ++i) enc.encode(intervals[2 * i], intervals[2 * i + 1]);
+    enc.finish();
+    *out_bits = enc.bits();
+    *out_bytes = buf.size();
+    NC_CHECK(out && cap >= buf.size(), NC_E_CAPACITY, "output needs %zu bytes", buf.size());
+    std::memcpy(out, buf.data(), buf.size());
+  });
+}
+
+nc_status nc_ac_decode_static(const uint8_t* in, size_t in_bytes, const uint32_t* cdf,
+                              uint32_t vocab, size_t n, int32_t* out) {
+  return guard([&] {
+    NC_CHECK(cdf && (n == 0 || out) && (in_bytes == 0 || in), NC_E_INVALID, "NULL pointer");
+    NC_CHECK(vocab >= 1 && cdf[0] == 0 && cdf[vocab] <= (1u << 24), NC_E_INVALID, "bad cdf");
+    for (uint32_t s = 0; s < vocab; ++s)
+      NC_CHECK(cdf[s] < cdf[s + 1], NC_E_INVALID, "cdf must be strictly increasing");
+    ArithDecoder dec(in, in_bytes, cdf[vocab]);
+    for (size_t i = 0; i < n; ++i) {
+      const uint32_t t = dec.target();
+      uint32_t lo = 0, hi = vocab - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (cdf[mid] <= t)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      dec.consume(cdf[lo], cdf[lo + 1]);
+      NC_CHECK(!dec.overrun(), NC_E_CORRUPT, "decoder ran past the end of the input");
+      out[i] = int32_t(lo);
+    }
+  });
+}
+
+}  // extern "C"

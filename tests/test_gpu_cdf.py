@@ -1,0 +1,115 @@
+"""GPU parity of the CDF-24 kernels (section 3.4) against the oracle quantiser: bit-exact on the
+same float32 probabilities, including adversarial rows."""
+import numpy as np
+import pytest
+
+from oracle.cdf import quantize_cdf
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+T24 = 1 << 24
+
+
+@pytest.fixture(scope="module")
+def nc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_19626_amd as m
+    return m
+
+
+def _gpu_cdf(nc, rows):
+    p = torch.from_numpy(np.ascontiguousarray(rows, dtype=np.float32)).cuda()
+    cdf, st = nc.quantize_cdf24(p)
+    torch.cuda.synchronize()
+    return cdf.cpu().numpy().view(np.uint32), st.cpu().numpy()
+
+
+def _check(nc, rows):
+    cdf, st = _gpu_cdf(nc, rows)
+    for r in range(rows.shape[0]):
+        assert st[r] == 0, r
+        ref = quantize_cdf(rows[r].astype(np.float32))
+        assert np.array_equal(cdf[r].astype(np.int64), ref), f"row {r}"
+
+
+def test_random_full_vocab_rows(nc):
+    rng = np.random.default_rng(0)
+    rows = np.stack([rng.dirichlet(np.full(49152, a)) for a in (0.01, 0.1, 1.0, 10.0)])
+    _check(nc, rows.astype(np.float32))
+
+
+def test_worked_examples(nc):
+    rows = np.full((1, 512), 2.0 ** -9, dtype=np.float32)
+    cdf, st = _gpu_cdf(nc, rows)
+    c = np.diff(cdf[0].astype(np.int64))
+    assert st[0] == 0 and c[0] == 33279 and np.all(c[1:] == 32767)
+    rows = np.full((1, 49152), 1.0 / 49152, dtype=np.float32)
+    cdf, _ = _gpu_cdf(nc, rows)
+    c = np.diff(cdf[0].astype(np.int64))
+    assert c[0] == 65876 and np.all(c[1:] == 340)
+    oh = np.zeros((1, 49152), np.float32)
+    oh[0, 40000] = 1.0
+    cdf, _ = _gpu_cdf(nc, oh)
+    c = np.diff(cdf[0].astype(np.int64))
+    assert c[40000] == T24 - 49152 + 1 and cdf[0, -1] == T24
+
+
+@pytest.mark.parametrize("v", [1, 2, 3, 5, 511, 4095, 4096, 4097, 5000, 12289, 49152, 65536])
+def test_ragged_vocab_sizes(nc, v):
+    rng = np.random.default_rng(v)
+    rows = np.stack([rng.dirichlet(np.full(v, 0.3)) for _ in range(3)]).astype(np.float32)
+    _check(nc, rows)
+
+
+def test_adversarial_rows(nc):
+    v = 49152
+    rng = np.random.default_rng(1)
+    rows = []
+    p = rng.dirichlet(np.full(v, 0.05)).astype(np.float32)
+    p[[10, 30000]] = p.max()                       # tie for the maximum: lowest index wins
+    rows.append(p / np.float32(p.sum()))
+    q = rng.dirichlet(np.full(v, 0.5)).astype(np.float32) * np.float32(1.00001)  # sum > 1
+    rows.append(q)
+    z = np.zeros(v, np.float32)
+    z[[0, v - 1]] = 0.5                             # mass at both ends, zeros elsewhere
+    rows.append(z)
+    s = rng.dirichlet(np.full(v, 0.05)).astype(np.float32)
+    s[::7] = np.float32(1e-40)                      # subnormals
+    rows.append(s)
+    t = np.full(v, np.float32(1.0 / v))
+    t[12345] = np.nextafter(t[12345], np.float32(1))  # near-integer products
+    rows.append(t)
+    _check(nc, np.stack(rows))
+
+
+def test_invalid_rows_flagged(nc):
+    v = 4096
+    good = np.full(v, 1.0 / v, np.float32)
+    bad = np.stack([good.copy() for _ in range(4)])
+    bad[0, 5] = np.nan
+    bad[1, 6] = -1e-3
+    bad[2, :] = 1.0                                  # mass far above the total
+    bad[3, 7] = 1.5
+    rows = np.concatenate([good[None], bad])
+    _, st = _gpu_cdf(nc, rows)
+    assert list(st) == [0, 1, 1, 1, 1]
+
+
+def test_batch_and_interval_lookup(nc):
+    rng = np.random.default_rng(2)
+    v = 49152
+    rows = np.stack([rng.dirichlet(np.full(v, 0.02)) for _ in range(64)]).astype(np.float32)
+    p = torch.from_numpy(rows).cuda()
+    cdf, st = nc.quantize_cdf24(p)
+    tok = rng.integers(0, v, size=64).astype(np.int32)
+    enc = nc.cdf_interval(cdf, torch.from_numpy(tok).cuda(), 0).cpu().numpy()
+    c = cdf.cpu().numpy().view(np.uint32).astype(np.int64)
+    targets = rng.integers(0, T24, size=64).astype(np.int32)
+    dec = nc.cdf_interval(cdf, torch.from_numpy(targets).cuda(), 1).cpu().numpy()
+    for r in range(64):
+        ref = quantize_cdf(rows[r])
+        assert np.array_equal(c[r], ref)
+        assert tuple(enc[r]) == (tok[r], ref[tok[r]], ref[tok[r] + 1])
+        s = int(np.searchsorted(ref, targets[r], side="right") - 1)
+        assert tuple(dec[r].astype(np.int64)) == (s, ref[s], ref[s + 1])
