@@ -9,6 +9,7 @@
 #include "coder.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "vocab_dev.hpp"
 
 namespace nc {
 static thread_local std::string g_last_error;
@@ -108,6 +109,38 @@ nc_status nc_ac_decode_static(const uint8_t* in, size_t in_bytes, const uint32_t
       NC_CHECK(!dec.overrun(), NC_E_CORRUPT, "decoder ran past the end of the input");
       out[i] = int32_t(lo);
     }
+  });
+}
+
+nc_status nc_ensemble_forward(const float* z, const float* b, const float* theta,
+                              const float* P, const int32_t* target, uint32_t rows,
+                              uint32_t vocab, uint32_t n_experts, float* loss, float* p,
+                              float* resp, void* stream) {
+  return guard([&] {
+    NC_CHECK(z && b && theta && target && resp && (n_experts == 1 || P), NC_E_INVALID,
+             "NULL pointer");
+    NC_CHECK(n_experts >= 1 && n_experts <= kMaxExperts, NC_E_INVALID, "n_experts in [1, 8]");
+    NC_CHECK(vocab >= 1 && vocab <= 262144u, NC_E_INVALID, "vocab must be in [1, 262144]");
+    if (rows == 0) return;
+    void* ws = pure_call_workspace(ensemble_workspace_bytes(int(rows), int(vocab)));
+    launch_ensemble_forward(z, b, theta, P, target, int(rows), int(vocab), int(n_experts), loss,
+                            p, resp, ws, static_cast<hipStream_t>(stream));
+  });
+}
+
+nc_status nc_ensemble_backward(const float* z, float* b, float* theta, const float* resp,
+                               const int32_t* target, const float* grad_loss, uint32_t rows,
+                               uint32_t vocab, uint32_t n_experts, float lr, float* grad_b,
+                               float* grad_theta, void* stream) {
+  return guard([&] {
+    NC_CHECK(z && b && theta && resp && target && grad_loss, NC_E_INVALID, "NULL pointer");
+    NC_CHECK(n_experts >= 1 && n_experts <= kMaxExperts, NC_E_INVALID, "n_experts in [1, 8]");
+    NC_CHECK(vocab >= 1 && vocab <= 262144u, NC_E_INVALID, "vocab must be in [1, 262144]");
+    if (rows == 0) return;
+    void* ws = pure_call_workspace(ensemble_workspace_bytes(int(rows), int(vocab)));
+    launch_ensemble_backward(z, b, theta, resp, target, grad_loss, int(rows), int(vocab),
+                             int(n_experts), lr, grad_b, grad_theta, ws,
+                             static_cast<hipStream_t>(stream));
   });
 }
 

@@ -1,0 +1,834 @@
+// Per-token vocabulary chain over a batch of streams (one row per stream and step):
+//   softmax of z + b (paper section 3.3 with the section 3.7 bias, temperature 1),
+//   coding distribution: bias head alone (warmup), n-gram alone (section 3.8 skip), the linear
+//   mix of section 3.6, or the softmax-gated ensemble,
+//   CDF-24 quantisation and scan (section 3.4) with the interval gather (encode) or the target
+//   search (decode) of section 3.9,
+//   online updates: bias head SGD (section 3.7), exponential-weights mixer (section 3.6), n-gram
+//   counts with the 64-slot cap (section 3.5), ensemble backward + SGD,
+//   n-gram prediction of the next position, its entropy and the skip decision (section 3.8).
+//
+// Rows are cut into 4096-entry segments, one 256-thread workgroup per (segment, row), and every
+// cross-segment combination runs in segment order, so each row's result is independent of the
+// launch shape and of the other rows.  No float atomics are used.
+#include "cdf_dev.hpp"
+#include "common.hpp"
+#include "vocab_dev.hpp"
+
+// The same probability must come out of the counting pass and the scanning pass bit for bit, so
+// no multiply-add contraction is allowed to differ between them: contraction is off here.
+#pragma clang fp contract(off)
+
+namespace nc {
+
+// ---- shared row arithmetic -----------------------------------------------------------------
+
+__device__ __forceinline__ LsePart lse_merge(LsePart a, LsePart b) {
+  const float M = fmaxf(a.m, b.m);
+  if (M == -INFINITY) return LsePart{-INFINITY, 0.f};
+  return LsePart{M, a.s * expf(a.m - M) + b.s * expf(b.m - M)};
+}
+
+// logsumexp of the row from its segment partials, combined in segment order
+__device__ __forceinline__ float row_lse(const LsePart* parts, int nseg) {
+  LsePart acc = parts[0];
+  for (int k = 1; k < nseg; ++k) acc = lse_merge(acc, parts[k]);
+  return acc.m + logf(acc.s);
+}
+
+struct RowIn {
+  const float* z;   // logits of the row (modes that use the LLM)
+  const float* b;   // bias vector of the stream
+  const float* png; // n-gram distribution of the stream
+  const float* pk;  // P_1..P_K (ensemble)
+  float lse;
+  int mode, use_head, K, V;
+  float w[kMaxExperts];
+};
+
+__device__ __forceinline__ float head_logit(const RowIn& R, int t) {
+  return R.use_head ? R.z[t] + R.b[t] : R.z[t];
+}
+
+// Coding probability of entry t; *pt receives the bias-head probability softmax(z + b)_t.
+__device__ __forceinline__ float row_prob(const RowIn& R, int t, float* pt) {
+  float q = 0.f;
+  if (R.mode != M_SKIP) q = expf(head_logit(R, t) - R.lse);
+  *pt = q;
+  if (R.mode == M_LLM) return q;
+  if (R.mode == M_SKIP) return R.png[t];
+  if (R.mode == M_MIX) return R.w[0] * q + R.w[1] * R.png[t];
+  float p = R.w[0] * q;
+  for (int j = 1; j <= R.K; ++j) p = p + R.w[j] * R.pk[(size_t)(j - 1) * R.V + t];
+  return p;
+}
+
+// Mixture / gate weights of a stream: mixer w = exp(log w); ensemble w = softmax(theta).
+__device__ __forceinline__ void row_weights(const VocabParams& P, const float* lw, float* w) {
+  if (P.ensemble) {
+    const int n = P.K + 1;
+    float mx = lw[0];
+    for (int j = 1; j < n; ++j) mx = fmaxf(mx, lw[j]);
+    float s = 0.f;
+    for (int j = 0; j < n; ++j) s += expf(lw[j] - mx);
+    for (int j = 0; j < n; ++j) w[j] = expf(lw[j] - mx) / s;
+  } else {
+    w[0] = expf(lw[0]);
+    w[1] = expf(lw[1]);
+  }
+}
+
+__device__ __forceinline__ bool uses_llm(int mode) { return mode != M_SKIP; }
+
+// ---- V1: logsumexp partials of z + b ---------------------------------------------------------
+
+__global__ __launch_bounds__(kSegThreads) void vocab_lse_kernel(VocabParams P, StreamState S,
+                                                                StepArgs A) {
+  __shared__ LsePart wl[kSegWaves];
+  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
+  const int s = A.rows[r];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int V = P.V;
+  LsePart part{-INFINITY, 0.f};
+  if (uses_llm(S.mode[s])) {
+    const float* z = A.z + (size_t)r * V;
+    const float* b = S.b + (size_t)s * V;
+    float u[4][4];
+    float m = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t t = seg_index(seg, j, tid, i);
+        u[j][i] = t < uint32_t(V) ? (P.use_head ? z[t] + b[t] : z[t]) : -INFINITY;
+        m = fmaxf(m, u[j][i]);
+      }
+    float sum = 0.f;
+    if (m != -INFINITY)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sum += expf(u[j][i] - m);
+    part = LsePart{m, sum};
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const LsePart o{__shfl_xor(part.m, d, 64), __shfl_xor(part.s, d, 64)};
+    part = (lane & d) ? lse_merge(o, part) : lse_merge(part, o);
+  }
+  if (lane == 0) wl[w] = part;
+  __syncthreads();
+  if (tid == 0) {
+    LsePart acc = wl[0];
+    for (int k = 1; k < kSegWaves; ++k) acc = lse_merge(acc, wl[k]);
+    A.lse_parts[(size_t)r * nseg + seg] = acc;
+  }
+}
+
+// Row setup shared by V2 and V3 (identical code, identical results).
+__device__ __forceinline__ RowIn make_row(const VocabParams& P, const StreamState& S,
+                                          const StepArgs& A, int r, int s, int nseg) {
+  RowIn R;
+  R.V = P.V;
+  R.K = P.K;
+  R.mode = S.mode[s];
+  R.use_head = P.use_head;
+  R.z = A.z + (size_t)r * P.V;
+  R.b = S.b + (size_t)s * P.V;
+  R.png = S.png + (size_t)s * P.V;
+  R.pk = S.pk ? S.pk + (size_t)s * P.K * P.V : nullptr;
+  R.lse = uses_llm(R.mode) ? row_lse(A.lse_parts + (size_t)r * nseg, nseg) : 0.f;
+  for (int j = 0; j < kMaxExperts; ++j) R.w[j] = 0.f;
+  row_weights(P, S.lw + (size_t)s * kMaxExperts, R.w);
+  return R;
+}
+
+__device__ __forceinline__ void row_probs(const RowIn& R, uint32_t seg, float (&p)[4][4],
+                                          float (&pt)[4][4]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = seg_index(seg, j, tid, i);
+      if (t < uint32_t(R.V)) {
+        p[j][i] = row_prob(R, int(t), &pt[j][i]);
+      } else {
+        p[j][i] = 0.f;
+        pt[j][i] = 0.f;
+      }
+    }
+}
+
+// ---- V2: count partials --------------------------------------------------------------------
+
+__global__ __launch_bounds__(kSegThreads) void vocab_count_kernel(VocabParams P, StreamState S,
+                                                                  StepArgs A) {
+  __shared__ SegLds L;
+  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
+  const int s = A.rows[r];
+  const RowIn R = make_row(P, S, A, r, s, nseg);
+  float p[4][4], pt[4][4];
+  row_probs(R, seg, p, pt);
+  const SegPartial sp = seg_reduce(p, seg, P.V, P.total - P.V, L);
+  if (threadIdx.x == 0) static_cast<SegPartial*>(A.seg_parts)[(size_t)r * nseg + seg] = sp;
+}
+
+// ---- V3: scan, interval / search, bias-head update -----------------------------------------
+
+__global__ __launch_bounds__(kSegThreads) void vocab_scan_kernel(VocabParams P, StreamState S,
+                                                                 StepArgs A) {
+  __shared__ SegLds L;
+  __shared__ int s_sym;
+  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
+  const int tid = threadIdx.x;
+  const int s = A.rows[r];
+  const int V = P.V;
+  if (tid < nseg) L.parts[tid] = static_cast<const SegPartial*>(A.seg_parts)[(size_t)r * nseg + tid];
+  if (tid == 0) s_sym = -1;
+  const RowIn R = make_row(P, S, A, r, s, nseg);
+  float p[4][4], pt[4][4];
+  row_probs(R, seg, p, pt);
+  __syncthreads();
+  const RowQuant q = seg_combine(L.parts, nseg, seg, V, P.total);
+  uint32_t base[4];
+  seg_scan(p, seg, V, q, base, L);
+  const int i_pos = S.ncommit[s];
+  const uint32_t key = A.decode ? A.targets[r] : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]);
+  int found = -1;
+  uint32_t fcl = 0, fch = 0;
+  float fp = 0.f, fpt = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t run = base[j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = seg_index(seg, j, tid, i);
+      if (t < uint32_t(V)) {
+        const uint32_t c = corrected_count(p[j][i], t, q);
+        const bool hit = A.decode ? (key >= run && key - run < c) : (t == key);
+        if (hit) {
+          found = int(t);
+          fcl = run;
+          fch = run + c;
+          fp = p[j][i];
+          fpt = pt[j][i];
+        }
+        if (A.dbg_cdf) A.dbg_cdf[(size_t)r * (V + 1) + t + 1] = run + c;
+        if (A.dbg_p) A.dbg_p[(size_t)r * V + t] = p[j][i];
+        if (A.dbg_pt) A.dbg_pt[(size_t)r * V + t] = pt[j][i];
+        run += c;
+      }
+    }
+  }
+  if (A.dbg_cdf && seg == 0 && tid == 0) A.dbg_cdf[(size_t)r * (V + 1)] = 0;
+  if (found >= 0 && !A.no_update) {
+    s_sym = found;
+    Outcome o;
+    o.sym = q.status ? -1 : found;
+    o.cl = fcl;
+    o.ch = fch;
+    o.mode = R.mode;
+    o.p = fp;
+    o.pt = fpt;
+    o.png = R.png[found];
+    o.lse = R.lse;
+    for (int k = 0; k < kMaxOrder; ++k)
+      o.pk[k] = (R.pk && k < P.K) ? R.pk[(size_t)k * V + found] : 0.f;
+    for (int k = 0; k < kMaxExperts; ++k) o.r[k] = 0.f;
+    if (R.mode == M_ENS) {
+      o.r[0] = R.w[0] * fpt / fp;
+      for (int k = 1; k <= P.K; ++k) o.r[k] = R.w[k] * o.pk[k - 1] / fp;
+    }
+    A.out[r] = o;
+    if (A.iv) {
+      A.iv[((size_t)s * S.maxT + i_pos) * 2 + 0] = fcl;
+      A.iv[((size_t)s * S.maxT + i_pos) * 2 + 1] = fch;
+    }
+    if (A.ptok) A.ptok[(size_t)s * S.maxT + i_pos] = fp;
+  }
+  if (found >= 0 && A.no_update) s_sym = found;
+  if (q.status && seg == 0 && tid == 0) {
+    // invalid distribution: report through the outcome; no symbol can be coded
+    Outcome o{};
+    o.sym = -1;
+    o.mode = R.mode;
+    A.out[r] = o;
+  }
+  // bias-head SGD step on -log ptilde(t*), section 3.7 (entries of this segment only)
+  if (P.use_head && !P.ensemble && (R.mode == M_LLM || R.mode == M_MIX) && !q.status &&
+      !A.no_update) {
+    __syncthreads();
+    const int sym = A.decode ? s_sym : int(key);
+    float* b = S.b + (size_t)s * V;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t t = seg_index(seg, j, tid, i);
+        if (t < uint32_t(V)) {
+          const float ind = int(t) == sym ? 1.f : 0.f;
+          b[t] = b[t] - P.head_lr * (pt[j][i] - ind);
+        }
+      }
+  }
+}
+
+// ---- V4: ensemble backward + SGD on b ------------------------------------------------------
+
+__global__ __launch_bounds__(kSegThreads) void ensemble_bias_kernel(VocabParams P, StreamState S,
+                                                                    StepArgs A) {
+  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
+  const int s = A.rows[r];
+  const Outcome o = A.out[r];
+  if (o.sym < 0 || o.mode != M_ENS) return;
+  const int V = P.V;
+  const float* z = A.z + (size_t)r * V;
+  float* b = S.b + (size_t)s * V;
+  const float r0 = o.r[0];
+  (void)nseg;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = seg_index(seg, j, threadIdx.x, i);
+      if (t < uint32_t(V)) {
+        const float q0 = expf(z[t] + b[t] - o.lse);
+        const float ind = int(t) == o.sym ? 1.f : 0.f;
+        b[t] = b[t] - P.head_lr * (r0 * (q0 - ind));
+      }
+    }
+}
+
+// ---- V5: n-gram + mixer / gate update with the coded symbol --------------------------------
+
+__device__ __forceinline__ uint32_t ctx_hash(const int32_t* toks, int k) {
+  uint64_t h = 0x9E3779B97F4A7C15ull * uint64_t(k + 1);
+  for (int i = 0; i < k; ++i) {
+    h ^= uint64_t(uint32_t(toks[i])) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+    h *= 0xBF58476D1CE4E5B9ull;
+  }
+  h ^= h >> 31;
+  return uint32_t(h);
+}
+
+// Probe the order-k table t for the context toks[0..k); returns the pool index or -1, and the
+// empty table slot where it would go in *ins.
+__device__ int ctx_find(const StreamState& S, size_t t, const int32_t* toks, int k, int* ins) {
+  const int32_t* keys = S.keys + t * S.cap * 4;
+  const int32_t* kidx = S.kidx + t * S.cap;
+  uint32_t h = ctx_hash(toks, k) & uint32_t(S.cap - 1);
+  for (int probe = 0; probe < S.cap; ++probe) {
+    const int id = kidx[h];
+    if (id < 0) {
+      *ins = int(h);
+      return -1;
+    }
+    bool eq = true;
+    for (int i = 0; i < k; ++i) eq = eq && keys[(size_t)h * 4 + i] == toks[i];
+    if (eq) return id;
+    h = (h + 1) & uint32_t(S.cap - 1);
+  }
+  *ins = -1;
+  return -1;
+}
+
+__global__ __launch_bounds__(64) void ngram_update_kernel(VocabParams P, StreamState S,
+                                                          StepArgs A) {
+  const int r = blockIdx.x;
+  const int s = A.rows[r];
+  const Outcome o = A.out[r];
+  const int k = threadIdx.x;
+  if (o.sym < 0) return;
+  const int i = S.ncommit[s];
+  const int32_t* hist = S.hist + (size_t)s * S.maxT;
+  const int sym = o.sym;
+  __syncthreads();
+  if (k == 0) {
+    if (A.decode) S.hist[(size_t)s * S.maxT + i] = sym;
+    if (P.use_ngram || P.ensemble) {
+      S.uni[(size_t)s * P.V + sym] += 1;
+      S.nseen[s] += 1;
+    }
+    float* lw = S.lw + (size_t)s * kMaxExperts;
+    if (o.mode == M_MIX) {
+      // exponential weights (section 3.6): log w_j += eta log p_j(t*), then renormalise
+      lw[0] = lw[0] + P.mix_eta * logf(o.pt);
+      lw[1] = lw[1] + P.mix_eta * logf(o.png);
+      const float mx = fmaxf(lw[0], lw[1]);
+      const float ls = mx + logf(expf(lw[0] - mx) + expf(lw[1] - mx));
+      lw[0] = lw[0] - ls;
+      lw[1] = lw[1] - ls;
+    } else if (o.mode == M_ENS) {
+      float w[kMaxExperts];
+      row_weights(P, lw, w);
+      for (int j = 0; j <= P.K; ++j) lw[j] = lw[j] - P.head_lr * (w[j] - o.r[j]);
+    }
+  }
+  if ((P.use_ngram || P.ensemble) && k >= 1 && k <= P.K) {
+    const size_t t = (size_t)s * P.K + (k - 1);
+    int32_t ctx[kMaxOrder];
+    // insert t* as a continuation of the order-k context ending at t_{i-1}
+    if (i >= k) {
+      for (int q = 0; q < k; ++q) ctx[q] = hist[i - k + q];
+      int ins = -1;
+      int id = ctx_find(S, t, ctx, k, &ins);
+      if (id < 0) {
+        if (ins >= 0 && S.nctx[t] < min(S.maxctx, P.ngram_max_contexts)) {
+          id = S.nctx[t]++;
+          for (int q = 0; q < 4; ++q) S.keys[(t * S.cap + ins) * 4 + q] = q < k ? ctx[q] : -1;
+          S.kidx[t * S.cap + ins] = id;
+          int32_t* sl = S.pool + (t * S.maxctx + id) * kSlots * 2;
+          sl[0] = sym;
+          sl[1] = 1;
+          S.pool_n[t * S.maxctx + id] = 1;
+          S.pool_sum[t * S.maxctx + id] = 1;
+        }
+      } else {
+        int32_t* sl = S.pool + (t * S.maxctx + id) * kSlots * 2;
+        const int n = S.pool_n[t * S.maxctx + id];
+        int j = 0;
+        while (j < n && sl[2 * j] != sym) ++j;
+        if (j < n) {
+          sl[2 * j + 1] += 1;
+          S.pool_sum[t * S.maxctx + id] += 1;
+        } else if (n < kSlots) {
+          sl[2 * n] = sym;
+          sl[2 * n + 1] = 1;
+          S.pool_n[t * S.maxctx + id] = n + 1;
+          S.pool_sum[t * S.maxctx + id] += 1;
+        } else {
+          int ev = 0;  // lowest count, lowest slot index on ties
+          for (int q = 1; q < kSlots; ++q)
+            if (sl[2 * q + 1] < sl[2 * ev + 1]) ev = q;
+          S.pool_sum[t * S.maxctx + id] += 1 - sl[2 * ev + 1];
+          sl[2 * ev] = sym;
+          sl[2 * ev + 1] = 1;
+        }
+      }
+    }
+    // context of the next position: t_{i-k+1} .. t_i (= t*)
+    int nid = -1;
+    if (i + 1 >= k) {
+      for (int q = 0; q < k - 1; ++q) ctx[q] = hist[i - k + 1 + q];
+      ctx[k - 1] = sym;
+      int ins;
+      nid = ctx_find(S, t, ctx, k, &ins);
+    }
+    S.next_ctx[(size_t)s * kMaxOrder + (k - 1)] = nid;
+  }
+  __syncthreads();
+  if (k == 0) S.ncommit[s] = i + 1;
+}
+
+// ---- V6: dense n-gram prediction of the current position ------------------------------------
+
+struct NgRow {
+  float lam[kMaxOrder];
+  int present[kMaxOrder];
+  float inv_norm;  // 1 / (N + V)
+};
+
+__device__ __forceinline__ NgRow ng_row(const VocabParams& P, const StreamState& S, int s) {
+  NgRow g;
+  for (int k = 1; k <= kMaxOrder; ++k) {
+    g.present[k - 1] = 0;
+    g.lam[k - 1] = 0.f;
+    if (k > P.K) continue;
+    const int id = S.next_ctx[(size_t)s * kMaxOrder + (k - 1)];
+    if (id < 0) continue;
+    const size_t t = (size_t)s * P.K + (k - 1);
+    const int n = S.pool_sum[t * S.maxctx + id];
+    if (n <= 0) continue;
+    g.present[k - 1] = 1;
+    g.lam[k - 1] = float(n) / (float(n) + P.ngram_eps);
+  }
+  g.inv_norm = 1.0f / float(S.nseen[s] + P.V);
+  return g;
+}
+
+__device__ __forceinline__ float ng_base(const StreamState& S, const NgRow& g, int s, int V,
+                                         int t) {
+  return float(S.uni[(size_t)s * V + t] + 1) * g.inv_norm;
+}
+
+__global__ __launch_bounds__(kSegThreads) void ngram_dense_kernel(VocabParams P, StreamState S,
+                                                                  const int32_t* rows,
+                                                                  NgPart* parts) {
+  __shared__ NgPart wl[kSegWaves];
+  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
+  const int s = rows[r];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int V = P.V;
+  const NgRow g = ng_row(P, S, s);
+  float h = 0.f, mx = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = seg_index(seg, j, tid, i);
+      if (t < uint32_t(V)) {
+        float pv = ng_base(S, g, s, V, int(t));
+        for (int k = 1; k <= P.K; ++k) {
+          if (g.present[k - 1]) pv = (1.0f - g.lam[k - 1]) * pv;
+          if (S.pk) S.pk[((size_t)s * P.K + (k - 1)) * V + t] = pv;
+        }
+        S.png[(size_t)s * V + t] = pv;
+        h = h - pv * log2f(pv);
+        mx = fmaxf(mx, pv);
+      }
+    }
+  h = wave_sum_f(h);
+  mx = wave_max_f(mx);
+  if (lane == 0) wl[w] = NgPart{h, mx};
+  __syncthreads();
+  if (tid == 0) {
+    NgPart acc = wl[0];
+    for (int k = 1; k < kSegWaves; ++k) {
+      acc.h += wl[k].h;
+      acc.mx = fmaxf(acc.mx, wl[k].mx);
+    }
+    parts[(size_t)r * nseg + seg] = acc;
+  }
+}
+
+// ---- V7: sparse n-gram entries, entropy, skip decision ---------------------------------------
+
+__global__ __launch_bounds__(256) void ngram_fix_kernel(VocabParams P, StreamState S,
+                                                        const int32_t* rows, const NgPart* parts,
+                                                        int nseg, StepOut* step_out,
+                                                        const Outcome* out) {
+  __shared__ int lt[kMaxOrder][kSlots], lc[kMaxOrder][kSlots], ln[kMaxOrder];
+  __shared__ float sh[256], smx[256];
+  const int r = blockIdx.x;
+  const int s = rows[r];
+  const int tid = threadIdx.x;
+  const int V = P.V;
+  const NgRow g = ng_row(P, S, s);
+  if (tid < kMaxOrder) ln[tid] = 0;
+  __syncthreads();
+  for (int e = tid; e < P.K * kSlots; e += blockDim.x) {
+    const int k = e / kSlots + 1, j = e % kSlots;
+    if (!g.present[k - 1]) continue;
+    const int id = S.next_ctx[(size_t)s * kMaxOrder + (k - 1)];
+    const size_t t = (size_t)s * P.K + (k - 1);
+    const int n = S.pool_n[t * S.maxctx + id];
+    if (j == 0) ln[k - 1] = n;
+    if (j < n) {
+      lt[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 0];
+      lc[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 1];
+    }
+  }
+  __syncthreads();
+  float dh = 0.f, dmx = 0.f;
+  for (int e = tid; e < P.K * kSlots; e += blockDim.x) {
+    const int k = e / kSlots + 1, j = e % kSlots;
+    if (j >= ln[k - 1]) continue;
+    const int tok = lt[k - 1][j];
+    bool owner = true;  // first occurrence over (order, slot) in increasing order
+    for (int k2 = 1; k2 < k && owner; ++k2)
+      for (int j2 = 0; j2 < ln[k2 - 1]; ++j2)
+        if (lt[k2 - 1][j2] == tok) {
+          owner = false;
+          break;
+        }
+    if (!owner) continue;
+    // P_k(tok) = lambda_k Phat_k(tok) + (1 - lambda_k) P_{k-1}(tok), k = 1..K (section 3.5)
+    float pv = ng_base(S, g, s, V, tok);
+    for (int k2 = 1; k2 <= P.K; ++k2) {
+      if (g.present[k2 - 1]) {
+        int cnt = 0;
+        for (int j2 = 0; j2 < ln[k2 - 1]; ++j2)
+          if (lt[k2 - 1][j2] == tok) cnt = lc[k2 - 1][j2];
+        const int id = S.next_ctx[(size_t)s * kMaxOrder + (k2 - 1)];
+        const float n = float(S.pool_sum[((size_t)s * P.K + (k2 - 1)) * S.maxctx + id]);
+        pv = g.lam[k2 - 1] * (float(cnt) / n) + (1.0f - g.lam[k2 - 1]) * pv;
+      }
+      if (S.pk) S.pk[((size_t)s * P.K + (k2 - 1)) * V + tok] = pv;
+    }
+    const float old = S.png[(size_t)s * V + tok];
+    S.png[(size_t)s * V + tok] = pv;
+    dh = dh + (old * log2f(old) - pv * log2f(pv));
+    dmx = fmaxf(dmx, pv);
+  }
+  sh[tid] = dh;
+  smx[tid] = dmx;
+  __syncthreads();
+  for (int d = blockDim.x / 2; d > 0; d >>= 1) {
+    if (tid < d) {
+      sh[tid] = sh[tid] + sh[tid + d];
+      smx[tid] = fmaxf(smx[tid], smx[tid + d]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    float H = 0.f, mx = 0.f;
+    for (int k = 0; k < nseg; ++k) {
+      H += parts[(size_t)r * nseg + k].h;
+      mx = fmaxf(mx, parts[(size_t)r * nseg + k].mx);
+    }
+    H = H + sh[0];
+    mx = fmaxf(mx, smx[0]);
+    S.H[s] = H;
+    S.pmax[s] = mx;
+    const int pos = S.ncommit[s];
+    int mode;
+    if (P.ensemble) {
+      mode = M_ENS;
+    } else {
+      const bool warm = pos < P.warmup;
+      bool skip = false;
+      if (P.use_skip && !warm) {
+        if (P.skip_mode == 1) skip = H < P.skip_bits;
+        if (P.skip_mode == 2) skip = mx >= P.skip_pmax;
+      }
+      mode = skip ? M_SKIP : ((warm || !P.use_mixer) ? M_LLM : M_MIX);
+    }
+    S.mode[s] = mode;
+    if (step_out) {
+      const Outcome o = out[r];
+      StepOut so{};
+      so.sym = o.sym;
+      so.cl = o.cl;
+      so.ch = o.ch;
+      so.next_mode = mode;
+      so.p = o.p;
+      step_out[r] = so;
+    }
+  }
+}
+
+// ---- reset -----------------------------------------------------------------------------------
+
+__global__ void state_reset_kernel(VocabParams P, StreamState S, int n, float w_llm) {
+  const int s = blockIdx.x;
+  if (s >= n) return;
+  const int V = P.V;
+  for (int t = threadIdx.x; t < V; t += blockDim.x) {
+    S.b[(size_t)s * V + t] = 0.f;
+    S.uni[(size_t)s * V + t] = 0;
+  }
+  if (threadIdx.x == 0) {
+    S.nseen[s] = 0;
+    S.ncommit[s] = 0;
+    float* lw = S.lw + (size_t)s * kMaxExperts;
+    for (int j = 0; j < kMaxExperts; ++j) lw[j] = 0.f;  // ensemble gate: uniform
+    if (!P.ensemble) {
+      lw[0] = logf(w_llm);
+      lw[1] = logf(1.0f - w_llm);
+    }
+    for (int k = 0; k < kMaxOrder; ++k) S.next_ctx[(size_t)s * kMaxOrder + k] = -1;
+    if (S.nctx)  // n-gram tables exist only when the n-gram (or the ensemble) is enabled
+      for (int k = 0; k < P.K; ++k) S.nctx[(size_t)s * P.K + k] = 0;
+    S.mode[s] = P.ensemble ? M_ENS : M_LLM;
+    S.H[s] = 0.f;
+    S.pmax[s] = 0.f;
+  }
+}
+
+// ---- standalone ensemble head (shared b and theta over a batch of rows) --------------------
+
+__device__ __forceinline__ void gate_weights(const float* theta, int n, float* w) {
+  float mx = theta[0];
+  for (int j = 1; j < n; ++j) mx = fmaxf(mx, theta[j]);
+  float s = 0.f;
+  for (int j = 0; j < n; ++j) s += expf(theta[j] - mx);
+  for (int j = 0; j < n; ++j) w[j] = expf(theta[j] - mx) / s;
+}
+
+// logsumexp partials of z_r + b per (segment, row)
+__global__ __launch_bounds__(kSegThreads) void ens_lse_kernel(const float* __restrict__ z,
+                                                              const float* __restrict__ b, int V,
+                                                              LsePart* __restrict__ parts) {
+  __shared__ LsePart wl[kSegWaves];
+  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  float u[4][4];
+  float m = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = seg_index(seg, j, tid, i);
+      u[j][i] = t < uint32_t(V) ? z[(size_t)r * V + t] + b[t] : -INFINITY;
+      m = fmaxf(m, u[j][i]);
+    }
+  float sum = 0.f;
+  if (m != -INFINITY)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sum += expf(u[j][i] - m);
+  LsePart part{m, sum};
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const LsePart o{__shfl_xor(part.m, d, 64), __shfl_xor(part.s, d, 64)};
+    part = (lane & d) ? lse_merge(o, part) : lse_merge(part, o);
+  }
+  if (lane == 0) wl[w] = part;
+  __syncthreads();
+  if (tid == 0) {
+    LsePart acc = wl[0];
+    for (int k = 1; k < kSegWaves; ++k) acc = lse_merge(acc, wl[k]);
+    parts[(size_t)r * nseg + seg] = acc;
+  }
+}
+
+// per row: lse, loss = -log p(t*), responsibilities r_j = w_j q_j(t*) / p(t*)
+__global__ void ens_row_kernel(const float* __restrict__ z, const float* __restrict__ b,
+                               const float* __restrict__ theta, const float* __restrict__ Pk,
+                               const int32_t* __restrict__ target, int rows, int V, int nexp,
+                               const LsePart* __restrict__ parts, int nseg,
+                               float* __restrict__ lse_out, float* __restrict__ loss,
+                               float* __restrict__ resp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float w[kMaxExperts];
+  gate_weights(theta, nexp, w);
+  const float lse = row_lse(parts + (size_t)r * nseg, nseg);
+  lse_out[r] = lse;
+  const int t = target[r];
+  float q[kMaxExperts];
+  q[0] = expf(z[(size_t)r * V + t] + b[t] - lse);
+  float p = w[0] * q[0];
+  for (int j = 1; j < nexp; ++j) {
+    q[j] = Pk[((size_t)r * (nexp - 1) + (j - 1)) * V + t];
+    p = p + w[j] * q[j];
+  }
+  if (loss) loss[r] = -logf(p);
+  for (int j = 0; j < nexp; ++j) resp[(size_t)r * nexp + j] = w[j] * q[j] / p;
+}
+
+__global__ void ens_lse_to_row_kernel(const LsePart* __restrict__ parts, int rows, int nseg,
+                                      float* __restrict__ lse) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < rows) lse[r] = row_lse(parts + (size_t)r * nseg, nseg);
+}
+
+// optional full coding distribution p_r
+__global__ void ens_prob_kernel(const float* __restrict__ z, const float* __restrict__ b,
+                                const float* __restrict__ theta, const float* __restrict__ Pk,
+                                int rows, int V, int nexp, const float* __restrict__ lse,
+                                float* __restrict__ p) {
+  const int r = blockIdx.y;
+  float w[kMaxExperts];
+  gate_weights(theta, nexp, w);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < V; t += gridDim.x * blockDim.x) {
+    float v = w[0] * expf(z[(size_t)r * V + t] + b[t] - lse[r]);
+    for (int j = 1; j < nexp; ++j) v = v + w[j] * Pk[((size_t)r * (nexp - 1) + (j - 1)) * V + t];
+    p[(size_t)r * V + t] = v;
+  }
+}
+
+// grad_b[t] = sum_r g_r r_{r,0} (q0_r(t) - 1[t = t*_r]), rows summed in order; SGD on b.
+__global__ void ens_grad_b_kernel(const float* __restrict__ z, float* __restrict__ b,
+                                  const float* __restrict__ resp, const int32_t* __restrict__ target,
+                                  const float* __restrict__ gl, int rows, int V, int nexp,
+                                  const float* __restrict__ lse, float lr,
+                                  float* __restrict__ gb) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < V; t += gridDim.x * blockDim.x) {
+    const float bt = b[t];
+    float g = 0.f;
+    for (int r = 0; r < rows; ++r) {
+      const float q0 = expf(z[(size_t)r * V + t] + bt - lse[r]);
+      const float ind = target[r] == t ? 1.f : 0.f;
+      g = g + gl[r] * resp[(size_t)r * nexp] * (q0 - ind);
+    }
+    if (gb) gb[t] = g;
+    if (lr != 0.f) b[t] = bt - lr * g;
+  }
+}
+
+// grad_theta[j] = sum_r g_r (w_j - r_{r,j}); SGD on theta (after every b thread read theta)
+__global__ void ens_grad_theta_kernel(float* __restrict__ theta, const float* __restrict__ resp,
+                                      const float* __restrict__ gl, int rows, int nexp, float lr,
+                                      float* __restrict__ gth) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float w[kMaxExperts];
+  gate_weights(theta, nexp, w);
+  float g[kMaxExperts];
+  for (int j = 0; j < nexp; ++j) {
+    g[j] = 0.f;
+    for (int r = 0; r < rows; ++r) g[j] = g[j] + gl[r] * (w[j] - resp[(size_t)r * nexp + j]);
+  }
+  for (int j = 0; j < nexp; ++j) {
+    if (gth) gth[j] = g[j];
+    if (lr != 0.f) theta[j] = theta[j] - lr * g[j];
+  }
+}
+
+size_t ensemble_workspace_bytes(int rows, int V) {
+  return size_t(rows) * (ceil_div(V, kSeg) * sizeof(LsePart) + sizeof(float)) + 256;
+}
+
+void launch_ensemble_forward(const float* z, const float* b, const float* theta, const float* Pk,
+                             const int32_t* target, int rows, int V, int nexp, float* loss,
+                             float* p, float* resp, void* ws, hipStream_t s) {
+  if (rows <= 0) return;
+  const int nseg = int(ceil_div(V, kSeg));
+  LsePart* parts = static_cast<LsePart*>(ws);
+  float* lse = reinterpret_cast<float*>(parts + (size_t)rows * nseg);
+  hipLaunchKernelGGL(ens_lse_kernel, dim3(nseg, rows), dim3(kSegThreads), 0, s, z, b, V, parts);
+  hipLaunchKernelGGL(ens_row_kernel, dim3(ceil_div(rows, 64)), dim3(64), 0, s, z, b, theta, Pk,
+                     target, rows, V, nexp, parts, nseg, lse, loss, resp);
+  if (p)
+    hipLaunchKernelGGL(ens_prob_kernel, dim3(ceil_div(V, 256), rows), dim3(256), 0, s, z, b,
+                       theta, Pk, rows, V, nexp, lse, p);
+  NC_HIP(hipGetLastError());
+}
+
+void launch_ensemble_backward(const float* z, float* b, float* theta, const float* resp,
+                              const int32_t* target, const float* gl, int rows, int V, int nexp,
+                              float lr, float* gb, float* gth, void* ws, hipStream_t s) {
+  if (rows <= 0) return;
+  const int nseg = int(ceil_div(V, kSeg));
+  LsePart* parts = static_cast<LsePart*>(ws);
+  float* lse = reinterpret_cast<float*>(parts + (size_t)rows * nseg);
+  hipLaunchKernelGGL(ens_lse_kernel, dim3(nseg, rows), dim3(kSegThreads), 0, s, z, b, V, parts);
+  // lse of each row (the forward's, recomputed in the same order)
+  hipLaunchKernelGGL(ens_lse_to_row_kernel, dim3(ceil_div(rows, 64)), dim3(64), 0, s, parts,
+                     rows, nseg, lse);
+  hipLaunchKernelGGL(ens_grad_b_kernel, dim3(ceil_div(V, 256)), dim3(256), 0, s, z, b, resp,
+                     target, gl, rows, V, nexp, lse, lr, gb);
+  hipLaunchKernelGGL(ens_grad_theta_kernel, dim3(1), dim3(64), 0, s, theta, resp, gl, rows, nexp,
+                     lr, gth);
+  NC_HIP(hipGetLastError());
+}
+
+// ---- launchers ------------------------------------------------------------------------------
+
+void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArgs& A,
+                       hipStream_t s) {
+  if (A.B <= 0) return;
+  const int nseg = int(ceil_div(P.V, kSeg));
+  const dim3 grid(nseg, A.B);
+  hipLaunchKernelGGL(vocab_lse_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
+  hipLaunchKernelGGL(vocab_count_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
+  hipLaunchKernelGGL(vocab_scan_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
+  if (!A.no_update) {
+    if (P.ensemble)
+      hipLaunchKernelGGL(ensemble_bias_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
+    hipLaunchKernelGGL(ngram_update_kernel, dim3(A.B), dim3(64), 0, s, P, S, A);
+  }
+  NC_HIP(hipGetLastError());
+}
+
+void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
+                          NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s) {
+  if (B <= 0) return;
+  const int nseg = int(ceil_div(P.V, kSeg));
+  hipLaunchKernelGGL(ngram_dense_kernel, dim3(nseg, B), dim3(kSegThreads), 0, s, P, S, rows,
+                     parts);
+  hipLaunchKernelGGL(ngram_fix_kernel, dim3(B), dim3(256), 0, s, P, S, rows, parts, nseg,
+                     step_out, out);
+  NC_HIP(hipGetLastError());
+}
+
+void launch_state_reset(const VocabParams& P, const StreamState& S, int n_streams, float w_llm,
+                        hipStream_t s) {
+  if (n_streams <= 0) return;
+  hipLaunchKernelGGL(state_reset_kernel, dim3(n_streams), dim3(256), 0, s, P, S, n_streams, w_llm);
+  NC_HIP(hipGetLastError());
+}
+
+}  // namespace nc

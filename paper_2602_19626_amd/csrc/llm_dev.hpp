@@ -1,0 +1,80 @@
+// Shared declarations of the transformer kernels (k_llm.hip) and the runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nc {
+
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
+enum AMode { A_NORM = 0, A_DIRECT = 1 };                    // fused RMSNorm prologue, or not
+enum Epi { E_STORE = 0, E_RESID = 1, E_GLU = 2, E_QKV = 3 };  // epilogues
+
+// Per-row metadata of a transformer pass: which stream, which position, which token.
+struct RowMeta {
+  int32_t stream;
+  int32_t pos;
+  int32_t tok;
+  int32_t pad;
+};
+
+// Arguments of one GEMM C[M][N] = A[M][K] W[N][K]^T (+ epilogue).
+struct GemmArgs {
+  int M, N, K;
+  const void* A;          // A_NORM: float x rows (ld = K); A_DIRECT: Prec rows (ld = K)
+  const int32_t* a_rows;  // optional gather: A row of output row m is a_rows[m]
+  const float* gain;      // A_NORM: RMSNorm gain [K]
+  float eps;
+  float a_scale;          // FP8: dequantisation scale of A (A_DIRECT) / quantisation (A_NORM)
+  float* a_amax;          // optional: max |normed A| (calibration; integer atomic max)
+  const void* W;          // Prec [N][K]
+  float w_scale;          // FP8 weight scale
+  // epilogue outputs
+  float* out_f32;         // E_STORE: [M][ldo]; E_RESID: residual x [M][ldo] (+=)
+  int ldo;
+  void* out_p;            // E_GLU: Prec h [M][N/2] (quantised with out_scale for FP8)
+  float out_scale;        // FP8 activation scale of the produced tensor (1/scale applied)
+  float* out_amax;        // optional: max |output| before quantisation (calibration)
+  // E_QKV
+  const RowMeta* rows;
+  const float* rope;      // [max_pos][hd/2][2] (cos, sin), built in float64, stored float32
+  void* q_out;            // attention precision [M][Hq][hd]
+  void* k_cache;          // [stream][kvh][R][hd] for this layer (stream stride kv_stride)
+  void* vt_cache;         // [stream][kvh][hd][R]
+  long long kv_stride;    // elements per stream in k_cache / vt_cache (one layer)
+  int Hq, Hk, hd, ring;
+};
+
+// Attention work item: a block of up to 16 (query, head) columns of one stream and kv head.
+// Column c maps to global column cc = c0 + c, query row row_base + cc / g and head
+// kvh * g + cc % g, with g = Hq / Hkv.
+struct AttnItem {
+  int32_t stream;
+  int32_t kvh;
+  int32_t row_base;
+  int32_t pos_base;
+  int32_t c0;
+  int32_t ncols;
+  int32_t pad[2];
+};
+
+struct AttnArgs {
+  const AttnItem* items;
+  int n_items;
+  const void* q;        // [rows][Hq][hd] attention precision
+  const void* k_cache;  // layer base, stream stride kv_stride
+  const void* vt_cache;
+  long long kv_stride;
+  void* out;            // O-projection A operand [rows][Hq*hd] (Prec of the GEMMs)
+  float out_scale;      // FP8 quantisation scale of the output
+  float* out_amax;      // optional calibration amax
+  int Hq, Hk, hd, ring, ctx_len, slide;
+  float scale_log2;     // log2(e) / sqrt(hd)
+};
+
+void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, bool small_m, hipStream_t s);
+void launch_attention(int prec_att, int prec_out, const AttnArgs& a, int waves, hipStream_t s);
+void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, hipStream_t s);
+void launch_convert(const float* src, void* dst, long long n, int prec, float inv_scale,
+                    hipStream_t s);
+
+}  // namespace nc

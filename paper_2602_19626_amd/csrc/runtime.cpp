@@ -1,44 +1,1077 @@
-// Context-based pipeline entry points (placeholder until the runtime lands).
+// Host runtime of the pipeline: context, device memory, transformer passes, and the encode /
+// decode / probe loops of paper Algorithm 1 and its mirror.  All numerics run in the kernels of
+// k_llm.hip, k_vocab.hip and k_cdf.hip; the arithmetic coder runs here on the host (section 3.9).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+#include "cdf_dev.hpp"
+#include "coder.hpp"
 #include "common.hpp"
+#include "llm_dev.hpp"
+#include "vocab_dev.hpp"
 
 using namespace nc;
 
+namespace {
+
+constexpr int kBOS = 0;
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    NC_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct Layer {
+  float *g_attn, *g_mlp;            // RMSNorm gains (float32)
+  void *Wqkv, *Wo, *Wgu, *Wd;       // GEMM precision
+  float *Wqkv32, *Wo32, *Wgu32, *Wd32;  // float32 copies (FP32 mode, FP8 calibration)
+  float sw_qkv = 1, sw_o = 1, sw_gu = 1, sw_d = 1;  // FP8 weight scales
+  float sa_qkv = 1, sa_o = 1, sa_gu = 1, sa_d = 1;  // FP8 activation scales
+};
+
+size_t prec_bytes(int p) { return p == P_F32 ? 4 : p == P_BF16 ? 2 : 1; }
+
+}  // namespace
+
+struct nc_ctx {
+  nc_config cfg{};
+  int prec = P_F32, att = P_F32;
+  int dev = 0;
+  hipStream_t st = nullptr;
+  int d = 0, hq = 0, hk = 0, hd = 0, F = 0, V = 0, nl = 0, R = 0;
+  // weights
+  std::vector<void*> allocs;
+  float* E32 = nullptr;
+  void* Elm = nullptr;
+  float sw_lm = 1, sa_lm = 1;
+  float* g_final = nullptr;
+  std::vector<Layer> layers;
+  bool fp8_ready = false;
+  DevBuf<float> amax;  // calibration amax slots
+  // rope
+  DevBuf<float> rope;
+  int rope_pos = 0;
+  // per-stream state
+  int S_alloc = 0, T_alloc = 0, n_streams = 0, maxT = 0;
+  StreamState S{};
+  DevBuf<float> b, png, pk, lw, Hd, pmaxd, hlast;
+  DevBuf<int32_t> uni, nseen, hist, ncommit, moded, next_ctx, keys, kidx, pool, pool_n, pool_sum,
+      nctx;
+  DevBuf<uint8_t> kc, vc;
+  long long kv_stride = 0;  // elements per stream per layer (one of K or V^T)
+  DevBuf<uint32_t> iv;
+  DevBuf<float> ptok;
+  // pass buffers
+  int rows_alloc = 0;
+  DevBuf<float> x;
+  DevBuf<uint8_t> qb, ob, hb;
+  DevBuf<RowMeta> rowsd;
+  DevBuf<AttnItem> itemsd;
+  DevBuf<int32_t> lastrow;  // per stream: row of its last position in the latest pass
+  // step buffers
+  DevBuf<float> z;
+  DevBuf<int32_t> steprows, arows;
+  DevBuf<uint32_t> targets;
+  DevBuf<LsePart> lsep;
+  DevBuf<SegPartial> segp;
+  DevBuf<NgPart> ngp;
+  DevBuf<Outcome> outc;
+  DevBuf<StepOut> sout;
+  DevBuf<float> dbgp, dbgpt;
+  DevBuf<uint32_t> dbgcdf;
+  // pinned host staging
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  // host mirrors
+  std::vector<std::vector<int32_t>> hhist;  // committed tokens per stream
+  std::vector<int> appended;                // x positions in the KV cache per stream
+  nc_stats stats{};
+  VocabParams vp{};
+
+  ~nc_ctx();
+};
+
+nc_ctx::~nc_ctx() {
+  if (dev >= 0) (void)hipSetDevice(dev);
+  if (st) (void)hipStreamSynchronize(st);
+  for (void* p : allocs) (void)hipFree(p);
+  DevBuf<float>* fb[] = {&amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
+                         &dbgp, &dbgpt};
+  for (auto* q : fb) q->release();
+  DevBuf<int32_t>* ib[] = {&uni, &nseen, &hist, &ncommit, &moded, &next_ctx, &keys, &kidx,
+                           &pool, &pool_n, &pool_sum, &nctx, &lastrow, &steprows, &arows};
+  for (auto* q : ib) q->release();
+  kc.release();
+  vc.release();
+  qb.release();
+  ob.release();
+  hb.release();
+  iv.release();
+  targets.release();
+  dbgcdf.release();
+  rowsd.release();
+  itemsd.release();
+  lsep.release();
+  segp.release();
+  ngp.release();
+  outc.release();
+  sout.release();
+  if (pin) (void)hipHostFree(pin);
+  if (st) (void)hipStreamDestroy(st);
+}
+
+namespace {
+
+void* dmalloc(nc_ctx* c, size_t bytes) {
+  void* p = nullptr;
+  NC_HIP(hipMalloc(&p, bytes));
+  c->allocs.push_back(p);
+  return p;
+}
+
+void* pinned(nc_ctx* c, size_t bytes) {
+  if (bytes > c->pin_bytes) {
+    if (c->pin) NC_HIP(hipHostFree(c->pin));
+    c->pin = nullptr;
+    NC_HIP(hipHostMalloc(&c->pin, bytes, hipHostMallocDefault));
+    c->pin_bytes = bytes;
+  }
+  return c->pin;
+}
+
+template <class T>
+void h2d(nc_ctx* c, T* dst, const T* src, size_t n) {
+  if (!n) return;
+  void* p = pinned(c, n * sizeof(T));
+  std::memcpy(p, src, n * sizeof(T));
+  NC_HIP(hipMemcpyAsync(dst, p, n * sizeof(T), hipMemcpyHostToDevice, c->st));
+  NC_HIP(hipStreamSynchronize(c->st));
+}
+
+template <class T>
+void d2h(nc_ctx* c, T* dst, const T* src, size_t n) {
+  if (!n) return;
+  void* p = pinned(c, n * sizeof(T));
+  NC_HIP(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyDeviceToHost, c->st));
+  NC_HIP(hipStreamSynchronize(c->st));
+  std::memcpy(dst, p, n * sizeof(T));
+}
+
+float host_amax(const float* w, size_t n) {
+  float m = 0.f;
+  for (size_t i = 0; i < n; ++i) m = std::max(m, std::fabs(w[i]));
+  return m;
+}
+
+// Upload a float32 matrix and convert it to the GEMM precision on the device.
+void* upload_weight(nc_ctx* c, const float* host, size_t n, float* scale_out, float** f32_out) {
+  float* w32 = static_cast<float*>(dmalloc(c, n * 4));
+  NC_HIP(hipMemcpy(w32, host, n * 4, hipMemcpyHostToDevice));
+  if (f32_out) *f32_out = w32;
+  if (c->prec == P_F32) {
+    if (scale_out) *scale_out = 1.f;
+    return w32;
+  }
+  float inv = 1.f;
+  if (c->prec == P_FP8) {
+    const float am = host_amax(host, n);
+    const float sc = am > 0 ? am / 448.f : 1.f;
+    if (scale_out) *scale_out = sc;
+    inv = 1.f / sc;
+  } else if (scale_out) {
+    *scale_out = 1.f;
+  }
+  void* wp = dmalloc(c, n * prec_bytes(c->prec));
+  launch_convert(w32, wp, (long long)n, c->prec, inv, c->st);
+  NC_HIP(hipStreamSynchronize(c->st));
+  return wp;
+}
+
+void build_rope(nc_ctx* c, int max_pos) {
+  if (max_pos <= c->rope_pos) return;
+  const int h2 = c->hd / 2;
+  std::vector<float> t((size_t)max_pos * h2 * 2);
+  for (int p = 0; p < max_pos; ++p)
+    for (int i = 0; i < h2; ++i) {
+      // angle p * theta^(-2i/hd) in float64, rounded once to float32
+      const double inv = std::pow((double)c->cfg.rope_theta, -2.0 * i / c->hd);
+      const double a = (double)p * inv;
+      t[((size_t)p * h2 + i) * 2 + 0] = (float)std::cos(a);
+      t[((size_t)p * h2 + i) * 2 + 1] = (float)std::sin(a);
+    }
+  c->rope.alloc(t.size());
+  NC_HIP(hipMemcpy(c->rope.p, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+  c->rope_pos = max_pos;
+}
+
+void ensure_rows(nc_ctx* c, int rows) {
+  if (rows <= c->rows_alloc) return;
+  const int r = std::max(rows, 64);
+  c->x.alloc((size_t)r * c->d);
+  // sized for float32 so that the calibration pass (float32 GEMMs) fits in any precision
+  c->qb.alloc((size_t)r * c->hq * c->hd * 4);
+  c->ob.alloc((size_t)r * c->hq * c->hd * 4);
+  c->hb.alloc((size_t)r * c->F * 4);
+  c->rowsd.alloc(r);
+  c->itemsd.alloc((size_t)r * c->hk + 64);
+  c->rows_alloc = r;
+}
+
+void ensure_step(nc_ctx* c, int B) {
+  const int nseg = int(ceil_div(c->V, kSeg));
+  c->z.alloc((size_t)B * c->V);
+  c->steprows.alloc(B);
+  c->arows.alloc(B);
+  c->targets.alloc(B);
+  c->lsep.alloc((size_t)B * nseg);
+  c->segp.alloc((size_t)B * nseg);
+  c->ngp.alloc((size_t)B * nseg);
+  c->outc.alloc(B);
+  c->sout.alloc(B);
+}
+
+// ---- one transformer pass over a batch of rows --------------------------------------------
+
+struct BodyOpts {
+  bool calib = false;  // FP32 weights with amax recording (FP8 calibration)
+};
+
+// Appends rows (stream, pos, token) to the KV caches and leaves each row's final residual in x.
+// Rows of one stream must be consecutive positions spanning fewer than `slide` positions.
+void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
+  const int n = int(rows.size());
+  if (!n) return;
+  ensure_rows(c, n);
+  // attention items: per stream run of consecutive rows, per kv head, 16 columns each
+  std::vector<AttnItem> items;
+  const int g = c->hq / c->hk;
+  for (int i = 0; i < n;) {
+    int j = i;
+    while (j + 1 < n && rows[j + 1].stream == rows[i].stream && rows[j + 1].pos == rows[j].pos + 1)
+      ++j;
+    const int nq = j - i + 1;
+    for (int kvh = 0; kvh < c->hk; ++kvh)
+      for (int c0 = 0; c0 < nq * g; c0 += 16) {
+        AttnItem it{};
+        it.stream = rows[i].stream;
+        it.kvh = kvh;
+        it.row_base = i;
+        it.pos_base = rows[i].pos;
+        it.c0 = c0;
+        it.ncols = std::min(16, nq * g - c0);
+        items.push_back(it);
+      }
+    i = j + 1;
+  }
+  if ((int)items.size() > (int)c->itemsd.n) c->itemsd.alloc(items.size());
+  {
+    const size_t b1 = n * sizeof(RowMeta), b2 = items.size() * sizeof(AttnItem);
+    uint8_t* p = static_cast<uint8_t*>(pinned(c, b1 + b2));
+    std::memcpy(p, rows.data(), b1);
+    std::memcpy(p + b1, items.data(), b2);
+    NC_HIP(hipMemcpyAsync(c->rowsd.p, p, b1, hipMemcpyHostToDevice, c->st));
+    NC_HIP(hipMemcpyAsync(c->itemsd.p, p + b1, b2, hipMemcpyHostToDevice, c->st));
+    NC_HIP(hipStreamSynchronize(c->st));
+  }
+  const bool small = n <= 64;
+  const int prec = o.calib ? P_F32 : c->prec;
+  const int att = o.calib ? P_F32 : c->att;
+  launch_embed(c->E32, c->rowsd.p, n, c->d, c->x.p, c->st);
+  const long long layer_kv = (long long)c->S_alloc * c->kv_stride * prec_bytes(c->att);
+  for (int l = 0; l < c->nl; ++l) {
+    Layer& L = c->layers[l];
+    float* am = o.calib ? c->amax.p + 4 * l : nullptr;
+    // QKV with RoPE and the KV-ring write
+    GemmArgs a{};
+    a.M = n;
+    a.N = (c->hq + 2 * c->hk) * c->hd;
+    a.K = c->d;
+    a.A = c->x.p;
+    a.gain = L.g_attn;
+    a.eps = c->cfg.norm_eps;
+    a.a_scale = L.sa_qkv;
+    a.a_amax = am ? am + 0 : nullptr;
+    a.W = o.calib ? (void*)L.Wqkv32 : L.Wqkv;
+    a.w_scale = o.calib ? 1.f : L.sw_qkv;
+    a.rows = c->rowsd.p;
+    a.rope = c->rope.p;
+    a.q_out = c->qb.p;
+    a.k_cache = c->kc.p + l * layer_kv;
+    a.vt_cache = c->vc.p + l * layer_kv;
+    a.kv_stride = c->kv_stride;
+    a.Hq = c->hq;
+    a.Hk = c->hk;
+    a.hd = c->hd;
+    a.ring = c->R;
+    launch_gemm(prec, A_NORM, E_QKV, a, small, c->st);
+    // attention
+    AttnArgs t{};
+    t.items = c->itemsd.p;
+    t.n_items = int(items.size());
+    t.q = c->qb.p;
+    t.k_cache = a.k_cache;
+    t.vt_cache = a.vt_cache;
+    t.kv_stride = c->kv_stride;
+    t.out = c->ob.p;
+    t.out_scale = L.sa_o;
+    t.out_amax = am ? am + 1 : nullptr;
+    t.Hq = c->hq;
+    t.Hk = c->hk;
+    t.hd = c->hd;
+    t.ring = c->R;
+    t.ctx_len = c->cfg.ctx_len;
+    t.slide = c->cfg.slide;
+    t.scale_log2 = float(1.4426950408889634 / std::sqrt((double)c->hd));
+    launch_attention(att, prec, t, items.size() < 2048 ? 8 : 4, c->st);
+    // O projection + residual
+    GemmArgs ob{};
+    ob.M = n;
+    ob.N = c->d;
+    ob.K = c->hq * c->hd;
+    ob.A = c->ob.p;
+    ob.a_scale = L.sa_o;
+    ob.W = o.calib ? (void*)L.Wo32 : L.Wo;
+    ob.w_scale = o.calib ? 1.f : L.sw_o;
+    ob.out_f32 = c->x.p;
+    ob.ldo = c->d;
+    launch_gemm(prec, A_DIRECT, E_RESID, ob, small, c->st);
+    // gate/up with SiLU
+    GemmArgs gu{};
+    gu.M = n;
+    gu.N = 2 * c->F;
+    gu.K = c->d;
+    gu.A = c->x.p;
+    gu.gain = L.g_mlp;
+    gu.eps = c->cfg.norm_eps;
+    gu.a_scale = L.sa_gu;
+    gu.a_amax = am ? am + 2 : nullptr;
+    gu.W = o.calib ? (void*)L.Wgu32 : L.Wgu;
+    gu.w_scale = o.calib ? 1.f : L.sw_gu;
+    gu.out_p = c->hb.p;
+    gu.out_scale = L.sa_d;
+    gu.out_amax = am ? am + 3 : nullptr;
+    launch_gemm(prec, A_NORM, E_GLU, gu, small, c->st);
+    // down projection + residual
+    GemmArgs dn{};
+    dn.M = n;
+    dn.N = c->d;
+    dn.K = c->F;
+    dn.A = c->hb.p;
+    dn.a_scale = L.sa_d;
+    dn.W = o.calib ? (void*)L.Wd32 : L.Wd;
+    dn.w_scale = o.calib ? 1.f : L.sw_d;
+    dn.out_f32 = c->x.p;
+    dn.ldo = c->d;
+    launch_gemm(prec, A_DIRECT, E_RESID, dn, small, c->st);
+  }
+  c->stats.body_rows += n;
+}
+
+// z[m] = final_norm(A[a_rows[m]]) E^T for m < M.
+void run_lm_head(nc_ctx* c, const float* A, const int32_t* a_rows, int M, float* zout,
+                 bool calib = false) {
+  GemmArgs a{};
+  a.M = M;
+  a.N = c->V;
+  a.K = c->d;
+  a.A = A;
+  a.a_rows = a_rows;
+  a.gain = c->g_final;
+  a.eps = c->cfg.norm_eps;
+  a.a_scale = c->sa_lm;
+  a.a_amax = calib ? c->amax.p + 4 * c->nl : nullptr;
+  a.W = calib ? (void*)c->E32 : c->Elm;
+  a.w_scale = calib ? 1.f : c->sw_lm;
+  a.out_f32 = zout;
+  a.ldo = c->V;
+  launch_gemm(calib ? P_F32 : c->prec, A_NORM, E_STORE, a, M <= 64, c->st);
+}
+
+__global__ void copy_rows_kernel(const float* x, const int32_t* src_rows, const int32_t* dst_rows,
+                                 int n, int d, float* out) {
+  const int r = blockIdx.x;
+  if (r >= n) return;
+  const long long s = src_rows[r], t = dst_rows[r];
+  for (int k = threadIdx.x; k < d; k += blockDim.x) out[t * d + k] = x[s * d + k];
+}
+
+// After a pass, keep each stream's last residual row (its newest position) in hlast.
+void save_last_rows(nc_ctx* c, const std::vector<RowMeta>& rows) {
+  std::vector<int32_t> src, dst;
+  for (size_t i = 0; i < rows.size(); ++i)
+    if (i + 1 == rows.size() || rows[i + 1].stream != rows[i].stream) {
+      src.push_back(int32_t(i));
+      dst.push_back(rows[i].stream);
+    }
+  const int n = int(src.size());
+  c->lastrow.alloc(2 * n + 2);
+  std::vector<int32_t> both(src);
+  both.insert(both.end(), dst.begin(), dst.end());
+  h2d(c, c->lastrow.p, both.data(), both.size());
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(n), dim3(256), 0, c->st, c->x.p, c->lastrow.p,
+                     c->lastrow.p + n, n, c->d, c->hlast.p);
+  NC_HIP(hipGetLastError());
+}
+
+// Append x positions [appended[s], upto] of each listed stream, in passes that never span a
+// slide boundary's worth of positions; the last pass holds every stream's newest position.
+void catch_up(nc_ctx* c, const std::vector<int>& streams, const std::vector<int>& upto) {
+  const int C = c->cfg.slide;
+  int npass = 0;
+  std::vector<int> nch(streams.size());
+  for (size_t k = 0; k < streams.size(); ++k) {
+    const int pend = upto[k] - c->appended[streams[k]] + 1;
+    nch[k] = pend > 0 ? (pend + C - 1) / C : 0;
+    npass = std::max(npass, nch[k]);
+  }
+  for (int p = 0; p < npass; ++p) {
+    std::vector<RowMeta> rows;
+    for (size_t k = 0; k < streams.size(); ++k) {
+      const int s = streams[k];
+      const int ci = p - (npass - nch[k]);
+      if (ci < 0) continue;
+      const int a = c->appended[s] + ci * C;
+      const int e = std::min(upto[k], a + C - 1);
+      for (int j = a; j <= e; ++j)
+        rows.push_back(RowMeta{s, j, j == 0 ? kBOS : c->hhist[s][j - 1], 0});
+    }
+    run_body(c, rows);
+    save_last_rows(c, rows);
+  }
+  for (size_t k = 0; k < streams.size(); ++k)
+    c->appended[streams[k]] = std::max(c->appended[streams[k]], upto[k] + 1);
+}
+
+StreamState make_state(nc_ctx* c) {
+  StreamState S{};
+  S.V = c->V;
+  S.K = c->cfg.ngram_order;
+  S.maxT = c->T_alloc;
+  S.cap = c->S.cap;
+  S.maxctx = c->S.maxctx;
+  S.b = c->b.p;
+  S.uni = c->uni.p;
+  S.nseen = c->nseen.p;
+  S.hist = c->hist.p;
+  S.ncommit = c->ncommit.p;
+  S.png = c->png.p;
+  S.pk = (c->cfg.features & NC_F_ENSEMBLE) ? c->pk.p : nullptr;
+  S.lw = c->lw.p;
+  S.mode = c->moded.p;
+  S.H = c->Hd.p;
+  S.pmax = c->pmaxd.p;
+  S.next_ctx = c->next_ctx.p;
+  S.keys = c->keys.p;
+  S.kidx = c->kidx.p;
+  S.pool = c->pool.p;
+  S.pool_n = c->pool_n.p;
+  S.pool_sum = c->pool_sum.p;
+  S.nctx = c->nctx.p;
+  return S;
+}
+
+bool ngram_on(const nc_ctx* c) {
+  return (c->cfg.features & (NC_F_NGRAM | NC_F_ENSEMBLE)) != 0;
+}
+
+void reset_streams(nc_ctx* c, int n, int maxT) {
+  NC_CHECK(n >= 1 && n <= c->cfg.max_streams, NC_E_INVALID, "n_streams must be in [1, %d]",
+           c->cfg.max_streams);
+  NC_CHECK(maxT >= 1, NC_E_INVALID, "max_tokens must be >= 1");
+  const int K = c->cfg.ngram_order;
+  const int V = c->V;
+  if (n > c->S_alloc || maxT > c->T_alloc) {
+    const int Sa = std::max(n, c->S_alloc), Ta = std::max(maxT, c->T_alloc);
+    int cap = 1;
+    while (cap < 2 * (Ta + 1)) cap <<= 1;
+    const int maxctx = std::min(Ta, c->cfg.ngram_max_contexts);
+    c->b.alloc((size_t)Sa * V);
+    c->png.alloc((size_t)Sa * V);
+    if (c->cfg.features & NC_F_ENSEMBLE) c->pk.alloc((size_t)Sa * K * V);
+    c->lw.alloc((size_t)Sa * kMaxExperts);
+    c->Hd.alloc(Sa);
+    c->pmaxd.alloc(Sa);
+    c->hlast.alloc((size_t)Sa * c->d);
+    c->uni.alloc((size_t)Sa * V);
+    c->nseen.alloc(Sa);
+    c->hist.alloc((size_t)Sa * Ta);
+    c->ncommit.alloc(Sa);
+    c->moded.alloc(Sa);
+    c->next_ctx.alloc((size_t)Sa * kMaxOrder);
+    c->nctx.alloc((size_t)Sa * K);
+    if (ngram_on(c)) {
+      c->keys.alloc((size_t)Sa * K * cap * 4);
+      c->kidx.alloc((size_t)Sa * K * cap);
+      c->pool.alloc((size_t)Sa * K * maxctx * kSlots * 2);
+      c->pool_n.alloc((size_t)Sa * K * maxctx);
+      c->pool_sum.alloc((size_t)Sa * K * maxctx);
+    }
+    c->kv_stride = (long long)c->hk * c->R * c->hd;
+    c->kc.release();
+    c->vc.release();
+    const size_t kvb = (size_t)c->nl * Sa * c->kv_stride * prec_bytes(c->att);
+    c->kc.alloc(kvb);
+    c->vc.alloc(kvb);
+    c->iv.alloc((size_t)Sa * Ta * 2);
+    c->ptok.alloc((size_t)Sa * Ta);
+    c->S_alloc = Sa;
+    c->T_alloc = Ta;
+    c->S.cap = cap;
+    c->S.maxctx = std::max(1, maxctx);
+    build_rope(c, Ta + 2);
+  }
+  c->n_streams = n;
+  c->maxT = maxT;
+  c->S = make_state(c);
+  if (ngram_on(c)) NC_HIP(hipMemsetAsync(c->kidx.p, 0xFF, c->kidx.n * 4, c->st));
+  NC_HIP(hipMemsetAsync(c->kc.p, 0, c->kc.n, c->st));
+  NC_HIP(hipMemsetAsync(c->vc.p, 0, c->vc.n, c->st));
+  NC_HIP(hipMemsetAsync(c->hlast.p, 0, c->hlast.n * 4, c->st));
+  launch_state_reset(c->vp, c->S, c->S_alloc, c->cfg.mix_w_llm, c->st);
+  ensure_step(c, std::max(n, 1));
+  if (ngram_on(c)) {
+    std::vector<int32_t> ids(n);
+    std::iota(ids.begin(), ids.end(), 0);
+    h2d(c, c->steprows.p, ids.data(), ids.size());
+    launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
+  }
+  NC_HIP(hipStreamSynchronize(c->st));
+  c->hhist.assign(n, {});
+  c->appended.assign(n, 0);
+}
+
+StepArgs step_args(nc_ctx* c, int B, bool decode) {
+  StepArgs A{};
+  A.B = B;
+  A.rows = c->steprows.p;
+  A.z = c->z.p;
+  A.decode = decode ? 1 : 0;
+  A.targets = c->targets.p;
+  A.lse_parts = c->lsep.p;
+  A.seg_parts = c->segp.p;
+  A.ng_parts = c->ngp.p;
+  A.out = c->outc.p;
+  A.step_out = c->sout.p;
+  return A;
+}
+
+// One coding step for rows steprows[0..B): updates and next-position prediction included.
+void vocab_commit_step(nc_ctx* c, const StepArgs& A) {
+  launch_vocab_step(c->vp, c->S, A, c->st);
+  if (ngram_on(c))
+    launch_ngram_predict(c->vp, c->S, A.rows, A.B, c->ngp.p, A.decode ? A.step_out : nullptr,
+                         A.out, c->st);
+}
+
+void check_config(const nc_config* cfg) {
+  NC_CHECK(cfg, NC_E_INVALID, "NULL config");
+  NC_CHECK(cfg->n_layers >= 0 && cfg->d_model > 0 && cfg->d_model % 16 == 0, NC_E_INVALID,
+           "d_model must be a positive multiple of 16");
+  NC_CHECK(cfg->n_heads > 0 && cfg->n_kv_heads > 0 && cfg->n_heads % cfg->n_kv_heads == 0,
+           NC_E_INVALID, "n_heads must be a multiple of n_kv_heads");
+  NC_CHECK(cfg->head_dim >= 16 && cfg->head_dim <= 64 && 64 % cfg->head_dim == 0, NC_E_INVALID,
+           "head_dim must be 16, 32 or 64");
+  NC_CHECK(cfg->d_ffn > 0 && cfg->d_ffn % 16 == 0, NC_E_INVALID, "d_ffn must be a multiple of 16");
+  NC_CHECK(cfg->vocab >= 2 && cfg->vocab <= 262144, NC_E_INVALID, "vocab must be in [2, 262144]");
+  NC_CHECK(cfg->cdf_total > (uint32_t)cfg->vocab && cfg->cdf_total <= (1u << 24), NC_E_INVALID,
+           "cdf_total must satisfy vocab < total <= 2^24");
+  NC_CHECK(cfg->slide > 0 && cfg->ctx_len >= cfg->slide && cfg->ctx_len % cfg->slide == 0 &&
+               (cfg->ctx_len + cfg->slide) % 16 == 0 && cfg->ctx_len + cfg->slide <= 2816,
+           NC_E_INVALID, "ctx_len must be a multiple of slide with ctx_len + slide <= 2816");
+  NC_CHECK(cfg->ngram_order >= 1 && cfg->ngram_order <= kMaxOrder, NC_E_INVALID,
+           "ngram_order must be in [1, 4]");
+  NC_CHECK(cfg->precision >= NC_FP32 && cfg->precision <= NC_FP8, NC_E_INVALID, "bad precision");
+  NC_CHECK(cfg->max_streams >= 1, NC_E_INVALID, "max_streams must be >= 1");
+  NC_CHECK(cfg->mix_w_llm > 0.f && cfg->mix_w_llm < 1.f, NC_E_INVALID, "mix_w_llm in (0, 1)");
+  NC_CHECK(cfg->ngram_eps > 0.f, NC_E_INVALID, "ngram_eps must be positive");
+}
+
+void validate_tokens(const nc_ctx* c, const int32_t* t, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    NC_CHECK(t[i] >= 0 && t[i] < c->V, NC_E_INVALID, "token %zu (%d) outside [0, %d)", i, t[i],
+             c->V);
+}
+
+}  // namespace
+
+// ---- C ABI ------------------------------------------------------------------------------------
+
 extern "C" {
-nc_status nc_create(const nc_config*, const float*, nc_ctx**) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+nc_status nc_create(const nc_config* cfg, const float* w, nc_ctx** out) {
+  return guard([&] {
+    NC_CHECK(out, NC_E_INVALID, "NULL out");
+    *out = nullptr;
+    check_config(cfg);
+    NC_CHECK(w, NC_E_INVALID, "NULL weights");
+    auto c = std::make_unique<nc_ctx>();
+    c->cfg = *cfg;
+    NC_HIP(hipGetDevice(&c->dev));
+    NC_HIP(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
+    c->prec = cfg->precision == NC_FP32 ? P_F32 : cfg->precision == NC_BF16 ? P_BF16 : P_FP8;
+    c->att = c->prec == P_F32 ? P_F32 : P_BF16;
+    c->d = cfg->d_model;
+    c->hq = cfg->n_heads;
+    c->hk = cfg->n_kv_heads;
+    c->hd = cfg->head_dim;
+    c->F = cfg->d_ffn;
+    c->V = cfg->vocab;
+    c->nl = cfg->n_layers;
+    c->R = cfg->ctx_len + cfg->slide;  // ring: any batch spanning < slide positions is safe
+    const size_t d = c->d, nqkv = (size_t)(c->hq + 2 * c->hk) * c->hd, F = c->F;
+    // flat layout: E, per layer (attn_norm, Wq, Wk, Wv, Wo, mlp_norm, Wg, Wu, Wd), final_norm
+    const float* p = w;
+    c->E32 = static_cast<float*>(dmalloc(c.get(), (size_t)c->V * d * 4));
+    NC_HIP(hipMemcpy(c->E32, p, (size_t)c->V * d * 4, hipMemcpyHostToDevice));
+    if (c->prec == P_F32) {
+      c->Elm = c->E32;
+    } else {
+      float* tmp = nullptr;
+      c->Elm = upload_weight(c.get(), p, (size_t)c->V * d, &c->sw_lm, &tmp);
+    }
+    p += (size_t)c->V * d;
+    std::vector<float> gu((size_t)2 * F * d);
+    for (int l = 0; l < c->nl; ++l) {
+      Layer L;
+      L.g_attn = static_cast<float*>(dmalloc(c.get(), d * 4));
+      NC_HIP(hipMemcpy(L.g_attn, p, d * 4, hipMemcpyHostToDevice));
+      p += d;
+      L.Wqkv = upload_weight(c.get(), p, nqkv * d, &L.sw_qkv, &L.Wqkv32);  // Wq, Wk, Wv adjacent
+      p += nqkv * d;
+      L.Wo = upload_weight(c.get(), p, d * c->hq * c->hd, &L.sw_o, &L.Wo32);
+      p += d * c->hq * c->hd;
+      L.g_mlp = static_cast<float*>(dmalloc(c.get(), d * 4));
+      NC_HIP(hipMemcpy(L.g_mlp, p, d * 4, hipMemcpyHostToDevice));
+      p += d;
+      // interleave gate and up rows in 16-row groups for the fused SiLU epilogue
+      const float* Wg = p;
+      const float* Wu = p + F * d;
+      for (size_t blk = 0; blk < F / 16; ++blk)
+        for (size_t r = 0; r < 16; ++r) {
+          std::memcpy(&gu[((2 * blk) * 16 + r) * d], Wg + (blk * 16 + r) * d, d * 4);
+          std::memcpy(&gu[((2 * blk + 1) * 16 + r) * d], Wu + (blk * 16 + r) * d, d * 4);
+        }
+      L.Wgu = upload_weight(c.get(), gu.data(), 2 * F * d, &L.sw_gu, &L.Wgu32);
+      p += 2 * F * d;
+      L.Wd = upload_weight(c.get(), p, d * F, &L.sw_d, &L.Wd32);
+      p += d * F;
+      c->layers.push_back(L);
+    }
+    c->g_final = static_cast<float*>(dmalloc(c.get(), d * 4));
+    NC_HIP(hipMemcpy(c->g_final, p, d * 4, hipMemcpyHostToDevice));
+    c->amax.alloc(4 * c->nl + 1);
+    c->fp8_ready = c->prec != P_FP8;
+    VocabParams& P = c->vp;
+    P.V = c->V;
+    P.total = cfg->cdf_total;
+    P.use_head = (cfg->features & NC_F_HEAD) ? 1 : 0;
+    P.use_ngram = (cfg->features & NC_F_NGRAM) ? 1 : 0;
+    P.use_skip = (cfg->features & NC_F_SKIP) && cfg->skip_mode != NC_SKIP_NONE ? 1 : 0;
+    P.use_mixer = (cfg->features & NC_F_MIXER) ? 1 : 0;
+    P.ensemble = (cfg->features & NC_F_ENSEMBLE) ? 1 : 0;
+    if (P.ensemble) P.use_head = 1;
+    P.K = cfg->ngram_order;
+    P.head_lr = cfg->head_lr;
+    P.mix_eta = cfg->mix_eta;
+    P.ngram_eps = cfg->ngram_eps;
+    P.ngram_max_contexts = cfg->ngram_max_contexts;
+    P.warmup = cfg->warmup;
+    P.skip_mode = cfg->skip_mode;
+    P.skip_bits = cfg->skip_entropy_bits;
+    P.skip_pmax = cfg->skip_pmax;
+    NC_HIP(hipStreamSynchronize(c->st));
+    *out = c.release();
+  });
 }
-void nc_destroy(nc_ctx*) {}
-nc_status nc_streams_reset(nc_ctx*, uint32_t, uint32_t) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+void nc_destroy(nc_ctx* c) { delete c; }
+
+nc_status nc_streams_reset(nc_ctx* c, uint32_t n, uint32_t maxT) {
+  return guard([&] {
+    NC_CHECK(c, NC_E_INVALID, "NULL context");
+    NC_HIP(hipSetDevice(c->dev));
+    reset_streams(c, int(n), int(maxT));
+  });
 }
-nc_status nc_calibrate_fp8(nc_ctx*, const int32_t*, size_t) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+nc_status nc_calibrate_fp8(nc_ctx* c, const int32_t* tokens, size_t n) {
+  return guard([&] {
+    NC_CHECK(c && tokens && n > 0, NC_E_INVALID, "bad arguments");
+    NC_CHECK(c->prec == P_FP8, NC_E_STATE, "context is not FP8");
+    NC_HIP(hipSetDevice(c->dev));
+    validate_tokens(c, tokens, n);
+    reset_streams(c, 1, int(n) + 1);
+    NC_HIP(hipMemsetAsync(c->amax.p, 0, c->amax.n * 4, c->st));
+    // FP32 passes over x_0..x_{n-1} (BOS, t_0, ..) recording every GEMM input's |max|
+    const auto att_save = c->att;
+    c->att = P_F32;
+    // the FP32 pass needs float32 KV caches: use a temporary allocation
+    DevBuf<uint8_t> k32, v32;
+    const size_t kvb = (size_t)c->nl * c->S_alloc * c->kv_stride * 4;
+    k32.alloc(kvb);
+    v32.alloc(kvb);
+    NC_HIP(hipMemsetAsync(k32.p, 0, kvb, c->st));
+    NC_HIP(hipMemsetAsync(v32.p, 0, kvb, c->st));
+    std::swap(c->kc, k32);
+    std::swap(c->vc, v32);
+    DevBuf<int32_t> ar;
+    try {
+      const int C = c->cfg.slide;
+      for (size_t a = 0; a < n; a += C) {
+        std::vector<RowMeta> rows;
+        for (size_t j = a; j < std::min(n, a + C); ++j)
+          rows.push_back(RowMeta{0, int(j), j == 0 ? kBOS : tokens[j - 1], 0});
+        BodyOpts o;
+        o.calib = true;
+        run_body(c, rows, o);
+        std::vector<int32_t> idx(rows.size());
+        std::iota(idx.begin(), idx.end(), 0);
+        ar.alloc(idx.size());
+        h2d(c, ar.p, idx.data(), idx.size());
+        DevBuf<float> zt;
+        zt.alloc(rows.size() * (size_t)c->V);
+        run_lm_head(c, c->x.p, ar.p, int(rows.size()), zt.p, true);
+        NC_HIP(hipStreamSynchronize(c->st));
+        zt.release();
+      }
+    } catch (...) {
+      std::swap(c->kc, k32);
+      std::swap(c->vc, v32);
+      k32.release();
+      v32.release();
+      ar.release();
+      c->att = att_save;
+      throw;
+    }
+    std::swap(c->kc, k32);
+    std::swap(c->vc, v32);
+    k32.release();
+    v32.release();
+    ar.release();
+    c->att = att_save;
+    std::vector<float> am(c->amax.n);
+    d2h(c, am.data(), c->amax.p, am.size());
+    auto sc = [](float m) { return m > 0 ? m / 448.f : 1.f; };
+    for (int l = 0; l < c->nl; ++l) {
+      c->layers[l].sa_qkv = sc(am[4 * l + 0]);
+      c->layers[l].sa_o = sc(am[4 * l + 1]);
+      c->layers[l].sa_gu = sc(am[4 * l + 2]);
+      c->layers[l].sa_d = sc(am[4 * l + 3]);
+    }
+    c->sa_lm = sc(am[4 * c->nl]);
+    c->fp8_ready = true;
+    reset_streams(c, 1, int(n) + 1);
+  });
 }
-nc_status nc_probs_for_context(nc_ctx*, uint32_t, const int32_t*, size_t, float*, nc_probe*) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+nc_status nc_probs_for_context(nc_ctx* c, uint32_t s, const int32_t* tokens, size_t n,
+                               float* probs, nc_probe* probe) {
+  return guard([&] {
+    NC_CHECK(c && probs && (n == 0 || tokens), NC_E_INVALID, "bad arguments");
+    NC_HIP(hipSetDevice(c->dev));
+    NC_CHECK(c->fp8_ready, NC_E_STATE, "FP8 context needs nc_calibrate_fp8 first");
+    NC_CHECK(int(s) < c->n_streams, NC_E_STATE, "stream %u not reset (call nc_streams_reset)", s);
+    NC_CHECK(int(n) < c->maxT, NC_E_STATE, "history longer than the reset max_tokens");
+    validate_tokens(c, tokens, n);
+    auto& h = c->hhist[s];
+    NC_CHECK(n >= h.size(), NC_E_STATE, "history is shorter than the committed tokens");
+    for (size_t i = 0; i < h.size(); ++i)
+      NC_CHECK(tokens[i] == h[i], NC_E_STATE, "history differs from the committed tokens at %zu",
+               i);
+    const int32_t sid = int32_t(s);
+    h2d(c, c->steprows.p, &sid, 1);
+    // commit the new tokens one by one, exactly as the encoder does
+    for (size_t j = h.size(); j < n; ++j) {
+      NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc + j, tokens + j, 4,
+                            hipMemcpyHostToDevice, c->st));
+      catch_up(c, {int(s)}, {int(j)});
+      run_lm_head(c, c->hlast.p, c->steprows.p, 1, c->z.p);
+      StepArgs A = step_args(c, 1, false);
+      A.step_out = nullptr;
+      vocab_commit_step(c, A);
+      h.push_back(tokens[j]);
+    }
+    // distribution of position n
+    catch_up(c, {int(s)}, {int(n)});
+    run_lm_head(c, c->hlast.p, c->steprows.p, 1, c->z.p);
+    c->dbgp.alloc(c->V);
+    c->dbgpt.alloc(c->V);
+    c->dbgcdf.alloc(c->V + 1);
+    StepArgs A = step_args(c, 1, true);
+    A.no_update = 1;
+    A.step_out = nullptr;
+    const uint32_t zero = 0;
+    h2d(c, c->targets.p, &zero, 1);
+    A.dbg_p = c->dbgp.p;
+    A.dbg_pt = c->dbgpt.p;
+    A.dbg_cdf = c->dbgcdf.p;
+    launch_vocab_step(c->vp, c->S, A, c->st);  // probe: no state update is launched
+    NC_HIP(hipStreamSynchronize(c->st));
+    d2h(c, probs, c->dbgp.p, c->V);
+    if (probe) {
+      int32_t mode = 0;
+      d2h(c, &mode, c->moded.p + s, 1);
+      probe->mode = mode;
+      probe->llm_ran = mode != M_SKIP;
+      float hv = 0, pm = 0, lw[2] = {0, 0};
+      d2h(c, &hv, c->Hd.p + s, 1);
+      d2h(c, &pm, c->pmaxd.p + s, 1);
+      d2h(c, lw, c->lw.p + (size_t)s * kMaxExperts, 2);
+      probe->entropy_bits = hv;
+      probe->pmax = pm;
+      probe->mix_w[0] = std::exp(lw[0]);
+      probe->mix_w[1] = std::exp(lw[1]);
+      if (probe->logits) d2h(c, probe->logits, c->z.p, c->V);
+      if (probe->ptilde) d2h(c, probe->ptilde, c->dbgpt.p, c->V);
+      if (probe->p_ngram) d2h(c, probe->p_ngram, c->png.p + (size_t)s * c->V, c->V);
+      if (probe->cdf) d2h(c, probe->cdf, c->dbgcdf.p, c->V + 1);
+    }
+  });
 }
-nc_status nc_mix_update(nc_ctx*, uint32_t, int32_t) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+nc_status nc_mix_update(nc_ctx* c, uint32_t s, int32_t token) {
+  return guard([&] {
+    NC_CHECK(c, NC_E_INVALID, "NULL context");
+    NC_HIP(hipSetDevice(c->dev));
+    NC_CHECK(int(s) < c->n_streams, NC_E_STATE, "stream %u not reset", s);
+    validate_tokens(c, &token, 1);
+    auto& h = c->hhist[s];
+    const size_t j = h.size();
+    NC_CHECK(int(j) + 1 < c->maxT, NC_E_STATE, "stream is full (max_tokens reached)");
+    const int32_t sid = int32_t(s);
+    h2d(c, c->steprows.p, &sid, 1);
+    NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc + j, &token, 4,
+                          hipMemcpyHostToDevice, c->st));
+    catch_up(c, {int(s)}, {int(j)});
+    run_lm_head(c, c->hlast.p, c->steprows.p, 1, c->z.p);
+    StepArgs A = step_args(c, 1, false);
+    A.step_out = nullptr;
+    vocab_commit_step(c, A);
+    NC_HIP(hipStreamSynchronize(c->st));
+    h.push_back(token);
+  });
 }
-nc_status nc_encode_stream(nc_ctx*, uint32_t, const int32_t* const*, const size_t*,
-                           uint8_t* const*, const size_t*, size_t*, uint64_t*) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
+                           const size_t* n_tokens, uint8_t* const* out, const size_t* out_cap,
+                           size_t* out_bytes, uint64_t* out_bits) {
+  return guard([&] {
+    NC_CHECK(c && tokens && n_tokens && out && out_cap && out_bytes && out_bits, NC_E_INVALID,
+             "NULL argument");
+    NC_HIP(hipSetDevice(c->dev));
+    NC_CHECK(c->fp8_ready, NC_E_STATE, "FP8 context needs nc_calibrate_fp8 first");
+    const int n = int(ns);
+    size_t maxn = 0;
+    bool cap_ok = true;
+    for (int s = 0; s < n; ++s) {
+      NC_CHECK(tokens[s] || n_tokens[s] == 0, NC_E_INVALID, "NULL token array");
+      validate_tokens(c, tokens[s], n_tokens[s]);
+      maxn = std::max(maxn, n_tokens[s]);
+      if (out_cap[s] < encode_bound(n_tokens[s])) {
+        cap_ok = false;
+        out_bytes[s] = encode_bound(n_tokens[s]);
+      }
+    }
+    NC_CHECK(cap_ok, NC_E_CAPACITY, "an output buffer is below nc_encode_bound");
+    const auto t0 = std::chrono::steady_clock::now();
+    reset_streams(c, n, int(maxn) + 1);
+    c->stats = nc_stats{};
+    // streams by decreasing length: the active ones at position i are a prefix
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return n_tokens[a] > n_tokens[b]; });
+    for (int s = 0; s < n; ++s) {
+      if (!n_tokens[s]) continue;
+      NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc, tokens[s], n_tokens[s] * 4,
+                            hipMemcpyHostToDevice, c->st));
+    }
+    NC_HIP(hipStreamSynchronize(c->st));
+    h2d(c, c->steprows.p, order.data(), order.size());
+    if (ngram_on(c))
+      launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
+    const int C = c->cfg.slide;
+    DevBuf<int32_t> seg_arows;
+    for (size_t a = 0; a < maxn; a += C) {
+      // prefill: x positions [a, a + C) of every stream still active (teacher forcing)
+      std::vector<RowMeta> rows;
+      std::vector<int> off(n, -1);
+      for (int k = 0; k < n; ++k) {
+        const int s = order[k];
+        if (n_tokens[s] <= a) break;
+        off[k] = int(rows.size());
+        for (size_t j = a; j < std::min(n_tokens[s], a + C); ++j)
+          rows.push_back(RowMeta{s, int(j), j == 0 ? kBOS : tokens[s][j - 1], 0});
+      }
+      run_body(c, rows);
+      const size_t seg_len = std::min((size_t)C, maxn - a);
+      std::vector<int32_t> ar(seg_len * n, 0);
+      std::vector<int> active(seg_len, 0);
+      for (size_t i = 0; i < seg_len; ++i)
+        for (int k = 0; k < n; ++k)
+          if (n_tokens[order[k]] > a + i) {
+            ar[i * n + k] = off[k] + int(i);
+            active[i] = k + 1;
+          }
+      seg_arows.alloc(ar.size());
+      h2d(c, seg_arows.p, ar.data(), ar.size());
+      for (size_t i = 0; i < seg_len; ++i) {
+        const int B = active[i];
+        run_lm_head(c, c->x.p, seg_arows.p + i * n, B, c->z.p);
+        StepArgs A = step_args(c, B, false);
+        A.step_out = nullptr;
+        A.iv = c->iv.p;
+        A.ptok = c->ptok.p;
+        vocab_commit_step(c, A);
+      }
+    }
+    NC_HIP(hipStreamSynchronize(c->st));
+    // host coder, one thread per stream
+    std::vector<std::vector<uint32_t>> ivs(n);
+    std::vector<std::vector<float>> pts(n);
+    for (int s = 0; s < n; ++s) {
+      ivs[s].resize(n_tokens[s] * 2);
+      pts[s].resize(n_tokens[s]);
+      if (!n_tokens[s]) continue;
+      NC_HIP(hipMemcpy(ivs[s].data(), c->iv.p + (size_t)s * c->T_alloc * 2, n_tokens[s] * 8,
+                       hipMemcpyDeviceToHost));
+      NC_HIP(hipMemcpy(pts[s].data(), c->ptok.p + (size_t)s * c->T_alloc, n_tokens[s] * 4,
+                       hipMemcpyDeviceToHost));
+    }
+    std::vector<std::vector<uint8_t>> bufs(n);
+    std::vector<uint64_t> bits(n, 0);
+    std::vector<int> bad(n, 0);
+    auto work = [&](int s) {
+      ArithEncoder enc(&bufs[s], c->cfg.cdf_total);
+      for (size_t i = 0; i < n_tokens[s]; ++i) {
+        const uint32_t cl = ivs[s][2 * i], ch = ivs[s][2 * i + 1];
+        if (!(cl < ch && ch <= c->cfg.cdf_total)) {
+          bad[s] = 1;
+          return;
+        }
+        enc.encode(cl, ch);
+      }
+      enc.finish();
+      bits[s] = enc.bits();
+    };
+    {
+      const int nt = std::min<int>(n, std::max(1u, std::thread::hardware_concurrency()));
+      std::vector<std::thread> th;
+      for (int w = 0; w < nt; ++w)
+        th.emplace_back([&, w] {
+          for (int s = w; s < n; s += nt) work(s);
+        });
+      for (auto& t : th) t.join();
+    }
+    for (int s = 0; s < n; ++s) {
+      NC_CHECK(!bad[s], NC_E_STATE, "stream %d produced an invalid interval", s);
+      NC_CHECK(bufs[s].size() <= out_cap[s], NC_E_CAPACITY, "stream %d output too large", s);
+      std::memcpy(out[s], bufs[s].data(), bufs[s].size());
+      out_bytes[s] = bufs[s].size();
+      out_bits[s] = bits[s];
+      c->stats.tokens += n_tokens[s];
+      c->stats.bits += double(bits[s]);
+      for (float p : pts[s]) c->stats.ideal_bits += -std::log2((double)p);
+    }
+    c->stats.seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
 }
-nc_status nc_decode_stream(nc_ctx*, uint32_t, const uint8_t* const*, const size_t*,
-                           const size_t*, int32_t* const*) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
+                           const size_t* in_bytes, const size_t* n_tokens,
+                           int32_t* const* tokens_out) {
+  return guard([&] {
+    NC_CHECK(c && in && in_bytes && n_tokens && tokens_out, NC_E_INVALID, "NULL argument");
+    NC_HIP(hipSetDevice(c->dev));
+    NC_CHECK(c->fp8_ready, NC_E_STATE, "FP8 context needs nc_calibrate_fp8 first");
+    const int n = int(ns);
+    size_t maxn = 0;
+    for (int s = 0; s < n; ++s) maxn = std::max(maxn, n_tokens[s]);
+    const auto t0 = std::chrono::steady_clock::now();
+    reset_streams(c, n, int(maxn) + 1);
+    c->stats = nc_stats{};
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return n_tokens[a] > n_tokens[b]; });
+    h2d(c, c->steprows.p, order.data(), order.size());
+    std::vector<ArithDecoder> dec;
+    dec.reserve(n);
+    for (int s = 0; s < n; ++s) dec.emplace_back(in[s], in_bytes[s], c->cfg.cdf_total);
+    std::vector<int32_t> mode(n);
+    d2h(c, mode.data(), c->moded.p, n);
+    std::vector<uint32_t> tg(n);
+    std::vector<StepOut> so(n);
+    for (size_t i = 0; i < maxn; ++i) {
+      int B = 0;
+      while (B < n && n_tokens[order[B]] > i) ++B;
+      std::vector<int> llm, upto;
+      for (int k = 0; k < B; ++k)
+        if (mode[order[k]] != M_SKIP) {
+          llm.push_back(order[k]);
+          upto.push_back(int(i));
+        }
+      if (!llm.empty()) {
+        catch_up(c, llm, upto);
+        run_lm_head(c, c->hlast.p, c->steprows.p, B, c->z.p);
+        c->stats.llm_rows += llm.size();
+      }
+      c->stats.skipped += B - llm.size();
+      for (int k = 0; k < B; ++k) tg[k] = dec[order[k]].target();
+      h2d(c, c->targets.p, tg.data(), B);
+      StepArgs A = step_args(c, B, true);
+      vocab_commit_step(c, A);
+      if (!ngram_on(c)) {
+        // no n-gram stage: pack the outcome here (mode stays LLM)
+        std::vector<Outcome> oc(B);
+        d2h(c, oc.data(), c->outc.p, B);
+        for (int k = 0; k < B; ++k) so[k] = StepOut{oc[k].sym, oc[k].cl, oc[k].ch, M_LLM, oc[k].p};
+      } else {
+        d2h(c, so.data(), c->sout.p, B);
+      }
+      for (int k = 0; k < B; ++k) {
+        const int s = order[k];
+        NC_CHECK(so[k].sym >= 0, NC_E_STATE, "invalid coding distribution on stream %d", s);
+        dec[s].consume(so[k].cl, so[k].ch);
+        NC_CHECK(!dec[s].overrun(), NC_E_CORRUPT, "stream %d: decoder ran past its input", s);
+        tokens_out[s][i] = so[k].sym;
+        c->hhist[s].push_back(so[k].sym);
+        mode[s] = so[k].next_mode;
+        c->stats.ideal_bits += -std::log2((double)so[k].p);
+      }
+    }
+    for (int s = 0; s < n; ++s) c->stats.tokens += n_tokens[s];
+    c->stats.seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
 }
-nc_status nc_get_stats(const nc_ctx*, nc_stats*) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
+
+nc_status nc_get_stats(const nc_ctx* c, nc_stats* out) {
+  return guard([&] {
+    NC_CHECK(c && out, NC_E_INVALID, "NULL argument");
+    *out = c->stats;
+  });
 }
-nc_status nc_ensemble_forward(const float*, const float*, const float*, const float*,
-                              const int32_t*, uint32_t, uint32_t, uint32_t, float*, float*,
-                              float*, void*) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
-}
-nc_status nc_ensemble_backward(const float*, float*, float*, const float*, const int32_t*,
-                               const float*, uint32_t, uint32_t, uint32_t, float, float*, float*,
-                               void*) {
-  return guard([&] { fail(NC_E_STATE, "not implemented"); });
-}
-}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""GPU parity of the whole per-token pipeline against the FP64 oracle (tiny 2-layer workload):
+logits, bias head, n-gram, mixer, modes, CDF-24 on the GPU's own probabilities, exact round trip,
+and batch invariance of the coded bytes."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pipeline as op
+from oracle.cdf import quantize_cdf
+from tests.nc_util import gpu_available, kl_bits, make_context
+
+pytestmark = pytest.mark.gpu
+
+WL = synth.WORKLOADS["tiny"]
+POS = [0, 1, 5, 99, 100, 101, 127, 128, 129, 160, 300, 777, 1500, 2047]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    toks = synth.workload_streams(WL)[0]
+    ctx, w = make_context(WL)
+    orc = op.encode(op.Settings.from_workload(WL), WL.shape, w, toks, record=POS, block=1,
+                    quantize=False)
+    return ctx, w, toks, orc
+
+
+def test_logits_and_distributions_match_oracle(setup):
+    ctx, w, toks, orc = setup
+    ctx.reset(1, len(toks) + 1)
+    worst_z = 0.0
+    for i in POS:
+        p, pr = ctx.probs_for_context(0, toks[:i], probe=True)
+        rec = orc.records[i]
+        assert pr["mode"] == rec["mode"], i
+        if rec["mode"] != op.MODE_SKIP:
+            worst_z = max(worst_z, float(np.max(np.abs(pr["logits"] - rec["z"]))))
+            assert np.max(np.abs(pr["ptilde"] - rec["ptilde"])) < 1e-5
+        if rec.get("p_ng") is not None:
+            assert np.max(np.abs(pr["p_ngram"] - rec["p_ng"])) < 1e-6
+            assert abs(pr["entropy_bits"] - rec["entropy"]) < 1e-3
+        assert np.max(np.abs(p - rec["p"])) < 1e-5
+        assert kl_bits(rec["p"], p) < 1e-6
+        # CDF-24 on the GPU's own float32 probabilities is bit-exact with the oracle quantiser
+        assert np.array_equal(pr["cdf"].astype(np.int64), quantize_cdf(p.astype(np.float32)))
+        assert pr["cdf"][-1] == 1 << 24
+    assert worst_z < 1e-3
+
+
+def test_encode_decode_roundtrip_and_gap(setup):
+    ctx, w, toks, orc = setup
+    data, bits = ctx.encode_stream([toks])
+    st = ctx.stats()
+    assert st["tokens"] == len(toks)
+    out = ctx.decode_stream(data, [len(toks)])
+    assert np.array_equal(out[0], toks)
+    gap = (bits[0] - orc.ideal_bits) / len(toks)
+    assert gap < 0.01, gap
+    # re-encoding gives the same bytes (deterministic)
+    data2, bits2 = ctx.encode_stream([toks])
+    assert data2 == data and bits2 == bits
+
+
+def test_batch_invariance_of_coded_bytes(setup):
+    ctx, w, toks, orc = setup
+    streams = [synth.make_stream(n, WL.shape.vocab, seed=s, span=WL.span)
+               for n, s in ((700, 11), (1300, 12), (257, 13))]
+    alone = [ctx.encode_stream([s])[0][0] for s in streams]
+    import paper_2602_19626_amd as nc
+    cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32", skip=WL.skip,
+                         mix_init=WL.mix_init, max_streams=3)
+    big = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+    together, _ = big.encode_stream(streams)
+    assert together == alone
+    dec = big.decode_stream(together, [len(s) for s in streams])
+    for a, b in zip(dec, streams):
+        assert np.array_equal(a, b)
+
+
+def test_ablation_switches_roundtrip(setup):
+    ctx, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    t = toks[:600]
+    for over in (dict(use_ngram=False, use_skip=False, use_mixer=False),
+                 dict(use_head=False), dict(use_mixer=False), dict(use_skip=False)):
+        cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, skip=WL.skip,
+                             mix_init=WL.mix_init, **over)
+        c = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+        data, bits = c.encode_stream([t])
+        assert np.array_equal(c.decode_stream(data, [len(t)])[0], t), over
+        s = op.Settings.from_workload(WL, **over)
+        ref = op.encode(s, WL.shape, w, t, quantize=False, block=1)
+        assert (bits[0] - ref.ideal_bits) / len(t) < 0.02, over
+
+
+def test_error_paths(setup):
+    ctx, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    with pytest.raises(nc.NacrithError) as e:
+        ctx.encode_stream([np.array([1, 2, 512], np.int32)])
+    assert e.value.status == 1
+    data, _ = ctx.encode_stream([toks[:200]])
+    with pytest.raises(nc.NacrithError) as e:
+        ctx.decode_stream([data[0][:3]], [200])       # truncated stream: decoder overrun
+    assert e.value.status in (5,)
