@@ -1,0 +1,184 @@
+"""Throughput of the per-token probability pipeline on one MI355X: tokens/s encode+decode.
+
+One step = encode every stream of the workload and decode it again (the whole hot path:
+transformer forward over the sliding KV cache, vocabulary softmax with the bias head, n-gram,
+mixer and skip, CDF-24 quantisation, host arithmetic coder).  Inputs are the seeded synthetic
+streams and random-init weights of the workload; they are resident on the host before the timed
+region and the weights are resident in HBM.
+
+Prints one JSON line with the headline value, the roofline of the profiled kernel class (timed
+live with HIP events on the library's stream) and the FP64 oracle timed on a bounded sample of the
+same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tokens/s encode+decode (135M-shape LM + CDF-24), bpb gap vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # dense, published
+KERNEL_SOURCES = {"qkv": "k_llm.hip", "attn": "k_llm.hip", "oproj": "k_llm.hip",
+                  "gateup": "k_llm.hip", "down": "k_llm.hip", "lmhead": "k_llm.hip",
+                  "vocab": "k_vocab.hip", "ngram": "k_vocab.hip"}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    p = os.path.join(ROOT, "paper_2602_19626_amd", "csrc", KERNEL_SOURCES[kernel])
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if taken on the current source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    t = json.load(open(p))
+    if t.get("source_sha") != kernel_source_hash(kernel):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, weights, stream, n_sample: int):
+    """The oracle (FP64 numpy + exact integer quantiser + Python-integer coder) on a prefix."""
+    from threadpoolctl import threadpool_info
+    from oracle import pipeline as op
+    s = op.Settings.from_workload(wl)
+    toks = stream[:n_sample]
+    t0 = time.perf_counter()
+    r = op.encode(s, wl.shape, weights, toks)
+    t1 = time.perf_counter()
+    out = op.decode(s, wl.shape, weights, r.data, len(toks))
+    t2 = time.perf_counter()
+    assert np.array_equal(out, toks), "oracle round trip failed"
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return r, {"value": round(len(toks) / (t2 - t0), 3), "unit": "tokens/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {len(toks)} tokens of stream 0, encode ({t1 - t0:.1f} s) + "
+                         f"decode ({t2 - t1:.1f} s), FP64 numpy with {threads} BLAS threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="full_fp32")
+    ap.add_argument("--kernel", default="gateup", help="kernel class for the roofline")
+    ap.add_argument("--max-len", type=int, default=None, help="truncate streams (quick runs)")
+    ap.add_argument("--n-streams", type=int, default=None)
+    ap.add_argument("--cpu-sample", type=int, default=250)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (streams are "
+              "independent and would be sharded by stream, one process per GPU)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2602_19626_amd as nc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = synth.WORKLOADS[args.workload]
+    streams = synth.workload_streams(wl, max_len=args.max_len, n_streams=args.n_streams)
+    n_tok = int(sum(len(s) for s in streams))
+    weights = synth.make_weights(wl.shape, wl.weight_seed)
+    cfg = nc.make_config(wl.shape, ngram_order=wl.ngram_order, precision=wl.precision,
+                         skip=wl.skip, mix_init=wl.mix_init, warmup=wl.warmup,
+                         head_lr=wl.head_lr, cdf_total=wl.cdf_total, ensemble=wl.ensemble,
+                         max_streams=len(streams))
+    ctx = nc.Context(cfg, synth.flat_weights(wl.shape, weights))
+    if wl.precision == "fp8":
+        ctx.calibrate_fp8(synth.make_stream(2048, wl.shape.vocab, synth.CALIBRATION_SEED,
+                                            span=wl.span))
+
+    def step():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        data, bits = ctx.encode_stream(streams)
+        te = time.perf_counter()
+        st_enc = ctx.stats()
+        out = ctx.decode_stream(data, [len(s) for s in streams])
+        td = time.perf_counter()
+        torch.cuda.synchronize()
+        return data, bits, out, te - t0, td - te, st_enc
+
+    for _ in range(args.warmup):
+        step()
+    ctx.profile(args.kernel)
+    t_enc = t_dec = 0.0
+    ok = True
+    for _ in range(args.steps):
+        data, bits, out, te, td, st_enc = step()
+        t_enc += te
+        t_dec += td
+        ok = ok and all(np.array_equal(a, b) for a, b in zip(out, streams))
+    prof = ctx.profile_read()
+    ctx.profile(None)
+    total_bits = float(sum(bits))
+
+    # roofline of the profiled kernel class
+    avg_ms = prof["ms"] / max(prof["launches"], 1)
+    gemm_classes = ("qkv", "oproj", "gateup", "down", "lmhead")
+    bound = "hbm"
+    achieved = prof["bytes"] / max(prof["ms"], 1e-9) / 1e6           # GB/s
+    peak, unit = HBM_PEAK_GBS, "GB/s"
+    ai = prof["flops"] / max(prof["bytes"], 1.0)
+    ridge = MFMA_PEAK_TFLOPS[wl.precision] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if args.kernel in gemm_classes + ("attn",) and ai > ridge:
+        bound = "mfma"
+        achieved = prof["flops"] / max(prof["ms"], 1e-9) / 1e9        # TFLOP/s
+        peak, unit = MFMA_PEAK_TFLOPS[wl.precision], "TFLOP/s"
+    traffic = load_traffic(args.kernel, args.workload)
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": args.kernel, "launches": prof["launches"],
+                "avg_launch_us": round(avg_ms * 1000, 3),
+                "algorithmic_bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
+                "algorithmic_flops_per_launch": round(prof["flops"] / max(prof["launches"], 1))}
+
+    line = {"metric": METRIC,
+            "value": round(args.steps * n_tok / (t_enc + t_dec), 2),
+            "unit": "tokens/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(1000 * (t_enc + t_dec) / args.steps, 2),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[wl.precision],
+            "data": "synthetic: seeded Zipf(1.1) token streams with 30% copied spans, "
+                    "random-init N(0, 0.02) weights of the 135M shape",
+            "config": {"workload": args.workload, "streams": len(streams), "tokens": n_tok,
+                       "precision": wl.precision, "ngram_order": wl.ngram_order,
+                       "skip": wl.skip, "ensemble": wl.ensemble},
+            "encode_tok_s": round(args.steps * n_tok / t_enc, 2),
+            "decode_tok_s": round(args.steps * n_tok / t_dec, 2),
+            "bits_per_token": round(total_bits / n_tok, 5),
+            "skip_rate": None, "roundtrip_exact": bool(ok),
+            "roofline": roofline}
+    dstat = ctx.stats()
+    line["skip_rate"] = round(dstat["skipped"] / max(dstat["tokens"], 1), 4)
+    line["gpu_ideal_bits_per_token"] = round(st_enc["ideal_bits"] / n_tok, 5)
+
+    if not args.no_cpu_baseline:
+        n_s = min(args.cpu_sample, len(streams[0]))
+        ref, cb = cpu_baseline(wl, weights, streams[0], n_s)
+        line["cpu_baseline"] = cb
+        # gap of the GPU coder against the oracle's ideal code length, same prefix
+        d, b = ctx.encode_stream([streams[0][:n_s]])
+        line["gap_bits_per_token_sample"] = round((b[0] - ref.ideal_bits) / n_s, 5)
+        line["gap_bpb_at_4_bytes_per_token"] = round(line["gap_bits_per_token_sample"] / 4.0, 5)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

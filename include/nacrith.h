@@ -179,6 +179,35 @@ nc_status nc_decode_stream(nc_ctx* ctx, uint32_t n_streams, const uint8_t* const
 /* Statistics of the last nc_encode_stream / nc_decode_stream call. */
 nc_status nc_get_stats(const nc_ctx* ctx, nc_stats* out);
 
+/* ---- measurement ----------------------------------------------------------------------------
+ * Kernel classes of the pipeline.  With profiling on for one class, the library records a pair
+ * of HIP events on its own stream around every launch of that class and accumulates the elapsed
+ * time, the launch count and the algorithmic bytes moved / flops done (from the launch shapes:
+ * GEMM weights + activations read + outputs written; attention keys/values of the window + q/o;
+ * vocabulary chain z, b, n-gram rows read and b written). */
+enum {
+  NC_K_QKV = 0,     /* RMSNorm + QKV GEMM + RoPE + KV-ring write */
+  NC_K_ATTN = 1,    /* GQA attention over the window */
+  NC_K_OPROJ = 2,   /* O projection + residual */
+  NC_K_GATEUP = 3,  /* RMSNorm + gate/up GEMM + SiLU gating */
+  NC_K_DOWN = 4,    /* down projection + residual */
+  NC_K_LMHEAD = 5,  /* final RMSNorm + tied output GEMM */
+  NC_K_VOCAB = 6,   /* softmax/head/mix + CDF-24 + interval/search + head/mixer/n-gram update */
+  NC_K_NGRAM = 7,   /* n-gram prediction, entropy and skip decision */
+  NC_K_COUNT = 8
+};
+typedef struct nc_kstat {
+  double ms;          /* summed event time of the launches */
+  uint64_t launches;
+  double bytes;       /* algorithmic bytes of those launches */
+  double flops;       /* algorithmic flops of those launches */
+} nc_kstat;
+
+/* Select the profiled kernel class (-1 = off) and clear its counters. */
+nc_status nc_profile(nc_ctx* ctx, int32_t kernel_class);
+/* Counters of the profiled class since nc_profile(). */
+nc_status nc_profile_read(nc_ctx* ctx, nc_kstat* out);
+
 /* ---- host arithmetic coder (section 3.9), exposed for testing and container tools --------- */
 
 /* Encode n intervals (host, n x 2 uint32: cl, ch with 0 <= cl < ch <= total) with the 32-bit

@@ -185,6 +185,18 @@ class Context:
         check(lib().nc_decode_stream(self._h, n, ins, inb, lens, outp))
         return outs
 
+    def profile(self, kernel_class):
+        """Time one kernel class with HIP events on the library's stream (None = off)."""
+        from ._lib import KERNEL_CLASSES
+        cls = -1 if kernel_class is None else KERNEL_CLASSES[kernel_class]
+        check(lib().nc_profile(self._h, cls))
+
+    def profile_read(self) -> dict:
+        from ._lib import NcKstat
+        k = NcKstat()
+        check(lib().nc_profile_read(self._h, C.byref(k)))
+        return {f: getattr(k, f) for f, _ in NcKstat._fields_}
+
     def stats(self) -> dict:
         s = NcStats()
         check(lib().nc_get_stats(self._h, C.byref(s)))

@@ -42,6 +42,14 @@ class NcStats(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class NcKstat(C.Structure):
+    _fields_ = [("ms", C.c_double), ("launches", C.c_uint64), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
+KERNEL_CLASSES = {"qkv": 0, "attn": 1, "oproj": 2, "gateup": 3, "down": 4, "lmhead": 5,
+                  "vocab": 6, "ngram": 7}
+
 _P = C.c_void_p
 _SIG = {
     "nc_last_error": (C.c_char_p, []),
@@ -57,6 +65,8 @@ _SIG = {
     "nc_encode_stream": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P, _P, _P]),
     "nc_decode_stream": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P]),
     "nc_get_stats": (C.c_int, [_P, C.POINTER(NcStats)]),
+    "nc_profile": (C.c_int, [_P, C.c_int32]),
+    "nc_profile_read": (C.c_int, [_P, C.POINTER(NcKstat)]),
     "nc_ac_encode": (C.c_int, [_P, C.c_size_t, C.c_uint32, _P, C.c_size_t, _P, _P]),
     "nc_ac_decode_static": (C.c_int, [_P, C.c_size_t, _P, C.c_uint32, C.c_size_t, _P]),
     "nc_ensemble_forward": (C.c_int, [_P, _P, _P, _P, _P, C.c_uint32, C.c_uint32, C.c_uint32,

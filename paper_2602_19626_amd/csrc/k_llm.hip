@@ -15,6 +15,9 @@
 
 #include <algorithm>
 
+// Prefill and decode must round every shared expression identically: no contraction.
+#pragma clang fp contract(off)
+
 namespace nc {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -99,17 +102,229 @@ __device__ __forceinline__ void atomic_max_abs(float* p, float v) {
 }
 
 // ---- GEMM -----------------------------------------------------------------------------------
+//
+// Arithmetic of every output element (the same in every kernel and tile shape):
+//   out = ((0 + P_0) + P_1) + ... + P_{S-1},  S = ceil(K / 64),
+//   P_s = the chain of MFMAs over the 64 K entries of part s, starting from zero, where
+//     f32 16x16x4:            16 steps, step t / lane group g consumes k = 16 g + t,
+//     bf16 / fp8 16x16x32:     2 steps, step t / lane group g consumes k = 32 t + 8 g .. + 7,
+//   with entries beyond K read as zero.
+// The tile kernel (many rows) sums the parts as it walks K; the split kernel (few rows) computes
+// each part in its own wave and a reduce kernel adds the parts in order.  Both then apply the same
+// epilogue function, so a row's outputs do not depend on how many rows are in the launch.
 
-constexpr int BK = 32;
+constexpr int KP = 64;
+
+// 1 / sqrt(mean(x^2) + eps) of one row: lanes stride over K, then a fixed xor-tree reduction.
+__device__ __forceinline__ float row_inv_rms(const float* x, int K, float eps, int lane) {
+  float ss = 0.f;
+  for (int k = lane; k < K; k += 64) {
+    const float v = x[k];
+    ss += v * v;
+  }
+  ss = wave_sum_f(ss);
+  return 1.0f / sqrtf(ss / float(K) + eps);
+}
+
+// ---- epilogue emitters ----
+
+__device__ __forceinline__ void emit_qkv_prec(const GemmArgs& a, int prec_att, int m, int n,
+                                              float v, float partner) {
+  const int hd = a.hd, h2 = hd / 2;
+  const int nq = a.Hq * hd, nk = a.Hk * hd;
+  const RowMeta rm = a.rows[m];
+  const int within = n % hd;
+  if (n < nq + nk) {  // rotate-half RoPE on q and k
+    const int i = within < h2 ? within : within - h2;
+    const float cs = a.rope[((long long)rm.pos * h2 + i) * 2 + 0];
+    const float sn = a.rope[((long long)rm.pos * h2 + i) * 2 + 1];
+    v = within < h2 ? v * cs - partner * sn : v * cs + partner * sn;
+  }
+  long long idx;
+  void* base;
+  if (n < nq) {
+    idx = (long long)m * nq + n;
+    base = a.q_out;
+  } else {
+    const int kv = n < nq + nk ? n - nq : n - nq - nk;
+    const int kvh = kv / hd;
+    const long long slot = rm.pos % a.ring;
+    const long long sb = (long long)rm.stream * a.kv_stride + (long long)kvh * a.ring * hd;
+    if (n < nq + nk) {
+      idx = sb + slot * hd + within;
+      base = a.k_cache;
+    } else {
+      idx = sb + (long long)within * a.ring + slot;
+      base = a.vt_cache;
+    }
+  }
+  if (prec_att == P_F32)
+    PT<P_F32>::store(base, idx, v, 1.f);
+  else
+    PT<P_BF16>::store(base, idx, v, 1.f);
+}
+
+template <int P>
+__device__ __forceinline__ float emit_glu(const GemmArgs& a, int m, int col, float g, float u) {
+  const float h = g / (1.0f + expf(-g)) * u;
+  const float oinv = (P == P_FP8) ? 1.0f / a.out_scale : 1.0f;
+  PT<P>::store(a.out_p, (long long)m * (a.N / 2) + col, h, oinv);
+  return fabsf(h);
+}
+
+// Column of the partner of q/k column n for RoPE (the same head, the other half).
+__device__ __forceinline__ int rope_partner(const GemmArgs& a, int n) {
+  const int h2 = a.hd / 2;
+  return (n % a.hd) < h2 ? n + h2 : n - h2;
+}
+
+// ---- operand fragments (from LDS or global, row-major with K contiguous) ----
+
+template <int P>
+struct Frag;
+template <>
+struct Frag<P_F32> {
+  typedef float T[16];  // 16 steps of one float
+  __device__ static void load(T& f, const uint8_t* row, int g) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const v4f v = *reinterpret_cast<const v4f*>(row + (16 * g + 4 * q) * 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f[4 * q + e] = v[e];
+    }
+  }
+  __device__ static void zero(T& f) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) f[t] = 0.f;
+  }
+  // straight from a global row (entries k0 + 16 g + 0..15, zero at or beyond K)
+  __device__ static void load_raw(T& f, const uint8_t* row, int k0, int K, int g) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 16 * g + 4 * q;
+      const v4f v = k < K ? *reinterpret_cast<const v4f*>(row + (long long)k * 4)
+                          : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f[4 * q + e] = v[e];
+    }
+  }
+  template <class N4>
+  __device__ static void load_norm(T& f, N4&& norm, int k0, int g, float, float& amax) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float v[4];
+      norm(k0 + 16 * g + 4 * q, v);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        f[4 * q + e] = v[e];
+        amax = fmaxf(amax, fabsf(v[e]));
+      }
+    }
+  }
+  __device__ static void mma(v4f& acc, const T& a, const T& b) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[t], acc, 0, 0, 0);
+  }
+};
+template <>
+struct Frag<P_BF16> {
+  typedef v4i T[2];
+  __device__ static void load(T& f, const uint8_t* row, int g) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) f[t] = *reinterpret_cast<const v4i*>(row + (32 * t + 8 * g) * 2);
+  }
+  __device__ static void zero(T& f) { f[0] = f[1] = v4i{0, 0, 0, 0}; }
+  __device__ static void load_raw(T& f, const uint8_t* row, int k0, int K, int g) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = k0 + 32 * t + 8 * g;
+      f[t] = k < K ? *reinterpret_cast<const v4i*>(row + (long long)k * 2) : v4i{0, 0, 0, 0};
+    }
+  }
+  template <class N4>
+  __device__ static void load_norm(T& f, N4&& norm, int k0, int g, float inv_scale, float& amax) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      alignas(16) uint8_t b[16];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float v[4];
+        norm(k0 + 32 * t + 8 * g + 4 * h, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) amax = fmaxf(amax, fabsf(v[e]));
+        PT<P_BF16>::put4(b + 8 * h, v, inv_scale);
+      }
+      f[t] = *reinterpret_cast<const v4i*>(b);
+    }
+  }
+  __device__ static void mma(v4f& acc, const T& a, const T& b) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[t]),
+                                                    __builtin_bit_cast(v8bf, b[t]), acc, 0, 0, 0);
+  }
+};
+template <>
+struct Frag<P_FP8> {
+  typedef long T[2];
+  __device__ static void load(T& f, const uint8_t* row, int g) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) f[t] = *reinterpret_cast<const long*>(row + 32 * t + 8 * g);
+  }
+  __device__ static void zero(T& f) { f[0] = f[1] = 0; }
+  __device__ static void load_raw(T& f, const uint8_t* row, int k0, int K, int g) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = k0 + 32 * t + 8 * g;
+      f[t] = k < K ? *reinterpret_cast<const long*>(row + k) : 0;
+    }
+  }
+  template <class N4>
+  __device__ static void load_norm(T& f, N4&& norm, int k0, int g, float inv_scale, float& amax) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      alignas(8) uint8_t b[8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float v[4];
+        norm(k0 + 32 * t + 8 * g + 4 * h, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) amax = fmaxf(amax, fabsf(v[e]));
+        PT<P_FP8>::put4(b + 4 * h, v, inv_scale);
+      }
+      f[t] = *reinterpret_cast<const long*>(b);
+    }
+  }
+  __device__ static void mma(v4f& acc, const T& a, const T& b) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[t], b[t], acc, 0, 0, 0);
+  }
+};
+
+// Normalised A values x * inv * gain for 4 consecutive k (the operand value before rounding).
+__device__ __forceinline__ void norm4(const float* xrow, const float* gain, int k, int K,
+                                      float inv, float (&v)[4]) {
+  if (k < K) {
+    const v4f x = *reinterpret_cast<const v4f*>(xrow + k);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = x[i] * inv * gain[k + i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = 0.f;
+  }
+}
+
+// ---- tile kernel (many rows): LDS-staged 64-wide K parts ----
 
 template <int P, int AM, int EPI, int WM, int WN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const GemmArgs a) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BM = WM * WAVES_M, BN = WN * WAVES_N;
   constexpr int ES = PT<P>::ES;
-  constexpr int ROWB = BK * ES + 16;  // padded LDS row (bytes)
+  constexpr int ROWB = KP * ES + 16;  // padded LDS row (bytes)
   constexpr int RB = WM / 16, CB = WN / 16;
-  constexpr int CPR = BK * ES / 16;  // 16-byte chunks per LDS row
+  constexpr int CPR = KP * ES / 16;  // 16-byte chunks per LDS row
   __shared__ __align__(16) uint8_t lds_a[BM * ROWB];
   __shared__ __align__(16) uint8_t lds_b[BN * ROWB];
   __shared__ float s_inv[BM];
@@ -126,49 +341,35 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
   }
   __syncthreads();
   if constexpr (AM == A_NORM) {
-    // inverse RMS of each A row, one wave per row, lanes striding over K in a fixed order
     const float* X = static_cast<const float*>(a.A);
     for (int r = wave; r < BM; r += NT / 64) {
       const int ar = s_arow[r];
-      float ss = 0.f;
-      if (ar >= 0)
-        for (int k = lane; k < K; k += 64) {
-          const float v = X[(long long)ar * K + k];
-          ss += v * v;
-        }
-      ss = wave_sum_f(ss);
-      if (lane == 0) s_inv[r] = 1.0f / sqrtf(ss / float(K) + a.eps);
+      const float inv = ar >= 0 ? row_inv_rms(X + (long long)ar * K, K, a.eps, lane) : 0.f;
+      if (lane == 0) s_inv[r] = inv;
     }
     __syncthreads();
   }
 
-  v4f acc[RB][CB];
+  v4f tot[RB][CB];
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < CB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < CB; ++j) tot[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
   float amax = 0.f;
   const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
+  const int fr = lane & 15, fg = lane >> 4;
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // ---- global -> LDS ----
+  for (int k0 = 0; k0 < K; k0 += KP) {
     if constexpr (AM == A_NORM) {
       const float* X = static_cast<const float*>(a.A);
-      for (int c = tid; c < BM * (BK / 4); c += NT) {
-        const int r = c / (BK / 4), kc = c % (BK / 4);
-        const int k = k0 + kc * 4;
+      for (int c = tid; c < BM * (KP / 4); c += NT) {
+        const int r = c / (KP / 4), kc = c % (KP / 4);
         const int ar = s_arow[r];
         float v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (ar >= 0 && k < K) {
-          const v4f x = *reinterpret_cast<const v4f*>(X + (long long)ar * K + k);
-          const float inv = s_inv[r];
+        if (ar >= 0) norm4(X + (long long)ar * K, a.gain, k0 + kc * 4, K, s_inv[r], v);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            v[i] = x[i] * inv * a.gain[k + i];
-            amax = fmaxf(amax, fabsf(v[i]));
-          }
-        }
+        for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(v[i]));
         PT<P>::put4(lds_a + r * ROWB + kc * 4 * ES, v, a_inv);
       }
     } else {
@@ -194,55 +395,19 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
       }
     }
     __syncthreads();
-    // ---- MFMA ----
-    const int fr = lane & 15, fg = lane >> 4;
-    if constexpr (P == P_BF16) {
-      v8bf af[RB], bf[CB];
+    typename Frag<P>::T af[RB], bf[CB];
 #pragma unroll
-      for (int i = 0; i < RB; ++i)
-        af[i] = __builtin_bit_cast(
-            v8bf, *reinterpret_cast<const v4i*>(lds_a + (wm * WM + i * 16 + fr) * ROWB + fg * 16));
+    for (int i = 0; i < RB; ++i) Frag<P>::load(af[i], lds_a + (wm * WM + i * 16 + fr) * ROWB, fg);
 #pragma unroll
-      for (int j = 0; j < CB; ++j)
-        bf[j] = __builtin_bit_cast(
-            v8bf, *reinterpret_cast<const v4i*>(lds_b + (wn * WN + j * 16 + fr) * ROWB + fg * 16));
+    for (int j = 0; j < CB; ++j) Frag<P>::load(bf[j], lds_b + (wn * WN + j * 16 + fr) * ROWB, fg);
 #pragma unroll
-      for (int i = 0; i < RB; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < CB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
-    } else if constexpr (P == P_FP8) {
-      long af[RB], bf[CB];
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-        af[i] = *reinterpret_cast<const long*>(lds_a + (wm * WM + i * 16 + fr) * ROWB + fg * 8);
-#pragma unroll
-      for (int j = 0; j < CB; ++j)
-        bf[j] = *reinterpret_cast<const long*>(lds_b + (wn * WN + j * 16 + fr) * ROWB + fg * 8);
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int j = 0; j < CB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bf[j], acc[i][j], 0, 0, 0);
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        float af[RB], bf[CB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i)
-          af[i] = *reinterpret_cast<const float*>(lds_a + (wm * WM + i * 16 + fr) * ROWB +
-                                                  (kk * 4 + fg) * 4);
-#pragma unroll
-        for (int j = 0; j < CB; ++j)
-          bf[j] = *reinterpret_cast<const float*>(lds_b + (wn * WN + j * 16 + fr) * ROWB +
-                                                  (kk * 4 + fg) * 4);
-#pragma unroll
-        for (int i = 0; i < RB; ++i)
-#pragma unroll
-          for (int j = 0; j < CB; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < CB; ++j) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        Frag<P>::mma(acc, af[i], bf[j]);
+        tot[i][j] += acc;
       }
-    }
     __syncthreads();
   }
   if (a.a_amax) {
@@ -251,7 +416,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
   }
 
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
-  const int fr = lane & 15, fg = lane >> 4;
+  constexpr int PATT = P == P_F32 ? P_F32 : P_BF16;
 
   if constexpr (EPI == E_STORE || EPI == E_RESID) {
 #pragma unroll
@@ -263,20 +428,16 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
           const int m = m0 + wm * WM + i * 16 + fg * 4 + e;
           const int n = n0 + wn * WN + j * 16 + fr;
           if (m < a.M && n < a.N) {
-            const float v = acc[i][j][e] * deq;
             float* o = a.out_f32 + (long long)m * a.ldo + n;
             if constexpr (EPI == E_RESID)
-              *o += v;
+              *o += tot[i][j][e] * deq;
             else
-              *o = v;
+              *o = tot[i][j][e] * deq;
           }
         }
   } else if constexpr (EPI == E_GLU) {
-    // W rows are interleaved in 16-row groups (gate block, up block, gate block, ...), so the
-    // even column block j holds gates and block j + 1 the matching up projections.
+    // W rows are interleaved in 16-row groups (gate, up, gate, up, ...)
     float omax = 0.f;
-    const float oinv = (P == P_FP8) ? 1.0f / a.out_scale : 1.0f;
-    const int half = a.N / 2;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -284,21 +445,16 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int m = m0 + wm * WM + i * 16 + fg * 4 + e;
-          const int nb = n0 + wn * WN + j * 16;  // first column of the gate block
+          const int nb = n0 + wn * WN + j * 16;
           const int col = (nb / 32) * 16 + fr;
-          if (m < a.M && col < half) {
-            const float g = acc[i][j][e] * deq, u = acc[i][j + 1][e] * deq;
-            const float h = g / (1.0f + expf(-g)) * u;
-            omax = fmaxf(omax, fabsf(h));
-            PT<P>::store(a.out_p, (long long)m * half + col, h, oinv);
-          }
+          if (m < a.M && col < a.N / 2)
+            omax = fmaxf(omax, emit_glu<P>(a, m, col, tot[i][j][e] * deq, tot[i][j + 1][e] * deq));
         }
     if (a.out_amax) {
       omax = wave_max_f(omax);
       if (lane == 0) atomic_max_abs(a.out_amax, omax);
     }
   } else if constexpr (EPI == E_QKV) {
-    // stage the tile in LDS, then rotate q and k pairs (i, i + hd/2) and scatter q, k, v.
     __shared__ float ct[BM][BN + 1];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -306,248 +462,540 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
       for (int j = 0; j < CB; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          ct[wm * WM + i * 16 + fg * 4 + e][wn * WN + j * 16 + fr] = acc[i][j][e] * deq;
+          ct[wm * WM + i * 16 + fg * 4 + e][wn * WN + j * 16 + fr] = tot[i][j][e] * deq;
     __syncthreads();
-    const int hd = a.hd, h2 = hd / 2;
-    const int nq = a.Hq * hd, nk = a.Hk * hd;
+    const int nqk = (a.Hq + a.Hk) * a.hd;
     for (int c = tid; c < BM * BN; c += NT) {
       const int r = c / BN, cn = c % BN;
       const int m = m0 + r, n = n0 + cn;
       if (m >= a.M || n >= a.N) continue;
-      const RowMeta rm = a.rows[m];
-      const int within = n % hd;
-      float v = ct[r][cn];
-      if (n < nq + nk) {
-        const int i = within < h2 ? within : within - h2;
-        const float cs = a.rope[((long long)rm.pos * h2 + i) * 2 + 0];
-        const float sn = a.rope[((long long)rm.pos * h2 + i) * 2 + 1];
-        const float other = within < h2 ? ct[r][cn + h2] : ct[r][cn - h2];
-        v = within < h2 ? v * cs - other * sn : v * cs + other * sn;
-      }
-      if (n < nq) {
-        if constexpr (P == P_F32)
-          PT<P_F32>::store(a.q_out, (long long)m * nq + n, v, 1.f);
-        else
-          PT<P_BF16>::store(a.q_out, (long long)m * nq + n, v, 1.f);
-      } else {
-        const int kv = n < nq + nk ? n - nq : n - nq - nk;
-        const int kvh = kv / hd;
-        const long long slot = rm.pos % a.ring;
-        const long long sb = (long long)rm.stream * a.kv_stride + (long long)kvh * a.ring * hd;
-        if (n < nq + nk) {
-          const long long idx = sb + slot * hd + within;
-          if constexpr (P == P_F32)
-            PT<P_F32>::store(a.k_cache, idx, v, 1.f);
-          else
-            PT<P_BF16>::store(a.k_cache, idx, v, 1.f);
+      const float partner = n < nqk ? ct[r][rope_partner(a, n) - n0] : 0.f;
+      emit_qkv_prec(a, PATT, m, n, ct[r][cn], partner);
+    }
+  }
+}
+
+// ---- split kernel (few rows): one workgroup per epilogue group ----
+//
+// A group is the set of 16-column blocks one epilogue needs together: a RoPE pair of blocks
+// {b, b + hd/32} for QKV (a single block when hd = 16), a gate/up block pair for the SiLU-gated MLP,
+// one block otherwise.  The group's (block, K-part) items are spread over up to 16 waves; each
+// item's partial (its part's MFMA chain from zero) goes to LDS, and after one barrier the
+// workgroup adds each output's parts in order and applies the epilogue.  No cross-workgroup
+// communication is needed.
+
+constexpr int SPLIT_WAVES = 16;
+
+__global__ void row_rms_kernel(const GemmArgs a, float* __restrict__ inv) {
+  const int m = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (m >= a.M) return;
+  const int ar = a.a_rows ? a.a_rows[m] : m;
+  const float v = row_inv_rms(static_cast<const float*>(a.A) + (long long)ar * a.K, a.K, a.eps,
+                              lane);
+  if (lane == 0) inv[ar] = v;
+}
+
+// Blocks of group gi: QKV pairs blocks (b, b + half) within a head, GLU pairs (2j, 2j + 1).
+__device__ __forceinline__ int group_block(int epi, int hd, int gi, int j) {
+  if (epi == E_QKV) {
+    const int nb = hd / 16;  // blocks per head
+    if (nb == 1) return gi;
+    const int half = nb / 2;
+    const int head = gi / half, r = gi % half;
+    return head * nb + r + j * half;
+  }
+  if (epi == E_GLU) return 2 * gi + j;
+  return gi;
+}
+
+template <int P, int AM, int EPI, int MB>
+__global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const GemmArgs a) {
+  constexpr int ES = PT<P>::ES;
+  constexpr int G = (EPI == E_GLU || EPI == E_QKV) ? 2 : 1;
+  extern __shared__ float lds[];  // [items][MB*16 rows][16 cols] partials, then inv[MB*16]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int K = a.K, M = a.M, N = a.N;
+  const int S = (K + KP - 1) / KP;
+  const int gi = blockIdx.x;
+  const int gsize = (EPI == E_QKV && a.hd == 16) ? 1 : G;
+  const int items = gsize * S;
+  float* part = lds;
+  float* s_inv = lds + items * MB * 256;
+  const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
+  float amax = 0.f;
+  // weight fragment of item it (W is read once; its loads are issued ahead of their use)
+  auto load_w = [&](int it, typename Frag<P>::T& bf) {
+    const int n = group_block(EPI, a.hd, gi, it / S) * 16 + fr;
+    if (n < N)
+      Frag<P>::load_raw(bf, static_cast<const uint8_t*>(a.W) + (long long)n * K * ES,
+                        (it % S) * KP, K, fg);
+    else
+      Frag<P>::zero(bf);
+  };
+  typename Frag<P>::T bnext;
+  if (wave < items) load_w(wave, bnext);
+  if constexpr (AM == A_NORM) {
+    for (int m = wave; m < M; m += nw) {
+      const int ar = a.a_rows ? a.a_rows[m] : m;
+      const float v = a.inv ? a.inv[ar]
+                            : row_inv_rms(static_cast<const float*>(a.A) + (long long)ar * K, K,
+                                          a.eps, lane);
+      if (lane == 0) s_inv[m] = v;
+    }
+    __syncthreads();
+  }
+  for (int it = wave; it < items; it += nw) {
+    const int k0 = (it % S) * KP;
+    typename Frag<P>::T bf;
+    __builtin_memcpy(&bf, &bnext, sizeof(bf));
+    if (it + nw < items) load_w(it + nw, bnext);
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb) {
+      const int mrow = rb * 16 + fr;
+      typename Frag<P>::T af;
+      if (mrow < M) {
+        const int ar = a.a_rows ? a.a_rows[mrow] : mrow;
+        if constexpr (AM == A_NORM) {
+          const float* xrow = static_cast<const float*>(a.A) + (long long)ar * K;
+          const float iv = s_inv[mrow];
+          auto nf = [&](int k, float (&v)[4]) { norm4(xrow, a.gain, k, K, iv, v); };
+          Frag<P>::load_norm(af, nf, k0, fg, a_inv, amax);
         } else {
-          const long long idx = sb + (long long)within * a.ring + slot;
-          if constexpr (P == P_F32)
-            PT<P_F32>::store(a.vt_cache, idx, v, 1.f);
-          else
-            PT<P_BF16>::store(a.vt_cache, idx, v, 1.f);
+          Frag<P>::load_raw(af, static_cast<const uint8_t*>(a.A) + (long long)ar * K * ES, k0, K,
+                            fg);
         }
+      } else {
+        Frag<P>::zero(af);
+      }
+      v4f acc = {0.f, 0.f, 0.f, 0.f};
+      Frag<P>::mma(acc, af, bf);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) part[(it * MB + rb) * 256 + (fg * 4 + e) * 16 + fr] = acc[e];
+    }
+  }
+  __syncthreads();
+  if (a.a_amax) {
+    amax = wave_max_f(amax);
+    if (lane == 0) atomic_max_abs(a.a_amax, amax);
+  }
+  const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
+  // output (m, block j, column c) = sum over parts s in order
+  auto sum = [&](int m, int j, int c) {
+    float v = 0.f;
+    for (int s = 0; s < S; ++s) {
+      const int it = j * S + s;
+      v += part[(it * MB + m / 16) * 256 + (m % 16) * 16 + c];
+    }
+    return v * deq;
+  };
+  if constexpr (EPI == E_GLU) {
+    float omax = 0.f;
+    for (int t = threadIdx.x; t < M * 16; t += blockDim.x) {
+      const int m = t / 16, c = t % 16;
+      const int col = gi * 16 + c;
+      if (col < N / 2) omax = fmaxf(omax, emit_glu<P>(a, m, col, sum(m, 0, c), sum(m, 1, c)));
+    }
+    if (a.out_amax) {
+      omax = wave_max_f(omax);
+      if (lane == 0) atomic_max_abs(a.out_amax, omax);
+    }
+  } else {
+    const int nqk = (a.Hq + a.Hk) * a.hd;
+    for (int t = threadIdx.x; t < M * gsize * 16; t += blockDim.x) {
+      const int m = t / (gsize * 16), j = (t / 16) % gsize, c = t % 16;
+      const int n = group_block(EPI, a.hd, gi, j) * 16 + c;
+      if (n >= N) continue;
+      const float v = sum(m, j, c);
+      if constexpr (EPI == E_STORE) {
+        a.out_f32[(long long)m * a.ldo + n] = v;
+      } else if constexpr (EPI == E_RESID) {
+        a.out_f32[(long long)m * a.ldo + n] += v;
+      } else {
+        float partner = 0.f;
+        if (n < nqk) {
+          if (a.hd == 16) {
+            partner = sum(m, 0, c < 8 ? c + 8 : c - 8);
+          } else {
+            partner = sum(m, 1 - j, c);
+          }
+        }
+        emit_qkv_prec(a, P == P_F32 ? P_F32 : P_BF16, m, n, v, partner);
       }
     }
   }
 }
 
 // ---- attention ------------------------------------------------------------------------------
+//
+// Keys of a query's window [s(pos), pos] are cut into 64-key chunks at fixed absolute positions
+// (4 MFMA blocks of 16), and chunks into groups of 16 (1,024 keys).  A chunk partial is one softmax
+// pass over its 64 keys:
+//   m = max score, p = 2^(score - m), l = sum p (fixed order), o = V^T P^T (4 chained MFMAs).
+// Partials are combined by the left fold
+//   (m, l, o) <- (M, l 2^(m - M) + l' 2^(m' - M), o 2^(m - M) + o' 2^(m' - M)),  M = max(m, m'),
+// first over the chunks of each group (from empty), then over the group results in order; the
+// output is o / l.  Chunks or groups outside a column's window are empty (-inf, 0, 0) and fold as a
+// no-op, so a column's result does not depend on the other columns of its launch.
+// S^T = K Q^T puts keys on MFMA rows and (query, head) pairs on columns, so the probabilities
+// leave the QK MFMA in the B-operand layout of the 16x16x16 P*V MFMA (lane: column l%16, keys
+// 4(l/16)..+3) and no transpose is needed.
 
-constexpr int KCH = 256;   // keys per chunk; chunks start at multiples of 256 (absolute positions)
-constexpr int MAXCH = 12;  // chunks per item: covers a window of ctx_len + slide <= 2,816 keys
+constexpr int KCH = 64;      // keys per chunk
+constexpr int GCH = 16;      // chunks per group
+constexpr int MAXG = 4;      // groups an item may span (window <= 2,048 keys + 15 query positions)
 constexpr int HDMAX = 64;
+constexpr int DEC_WAVES = 16;
 
 __device__ __forceinline__ int window_start(int pos, int L, int C) {
   return pos < L ? 0 : C * (1 + (pos - L) / C);
 }
 
-// One workgroup per item; wave w handles chunks w, w + NW, ...  Per chunk and column: online
-// softmax over 16-key blocks with S^T = K Q^T (keys are MFMA rows, columns are (query, head)
-// pairs), so the probabilities come out of the QK MFMA already in the B-operand layout of the
-// 16x16x16 P*V MFMA (lane: column l%16, keys 4(l/16)..+3).  Partials (m, l, o) go to LDS and are
-// combined over chunks in increasing order by one fixed formula.
-template <int PA, int PO, int NW>
-__global__ __launch_bounds__(64 * NW) void attention_kernel(const AttnArgs a) {
-  __shared__ float pm[MAXCH][16], pl[MAXCH][16];
-  __shared__ float po[MAXCH][16][HDMAX + 1];
-  const AttnItem it = a.items[blockIdx.x];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = a.Hq / a.Hk, hd = a.hd, L = a.ctx_len, C = a.slide;
-  const int col = lane & 15, grp = lane >> 4;
+struct AttnCol {
+  bool valid;
+  int pos, cs, row, head;
+};
 
-  // this lane's column
-  const int cc = it.c0 + col;
-  const bool cvalid = col < it.ncols;
-  const int qo = cc / g;
-  const int head = it.kvh * g + cc % g;
-  const int pos = it.pos_base + qo;
-  const int row = it.row_base + qo;
-  const int cs = window_start(pos, L, C);
-  // item key range: first column has the smallest position
-  const int kmin = window_start(it.pos_base + it.c0 / g, L, C);
-  const int kmax = it.pos_base + (it.c0 + it.ncols - 1) / g;
-  const int ch0 = kmin / KCH, nch = kmax / KCH - ch0 + 1;
+struct ChunkState {
+  float m, l;
+  v4f o[HDMAX / 16];  // o[hb][j]: hd index hb*16 + 4 (lane/16) + j of column lane%16
+};
 
-  const long long sbase = (long long)it.stream * a.kv_stride + (long long)it.kvh * a.ring * hd;
-  const int nkstep = PA == P_BF16 ? (hd + 31) / 32 : hd / 4;
-  const int nhb = hd / 16;
-
-  // Q^T operand (B of the QK MFMA): column col, hd entries
-  v8bf qb[2];
-  float qf[HDMAX / 4];
-  {
-    const long long qbase = ((long long)row * a.Hq + head) * hd;
-    if constexpr (PA == P_BF16) {
-      const uint16_t* Q = static_cast<const uint16_t*>(a.q);
+__device__ __forceinline__ void state_empty(ChunkState& a) {
+  a.m = -INFINITY;
+  a.l = 0.f;
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        uint16_t t[8];
+  for (int hb = 0; hb < HDMAX / 16; ++hb) a.o[hb] = v4f{0.f, 0.f, 0.f, 0.f};
+}
+
+__device__ __forceinline__ void fold(ChunkState& a, const ChunkState& b, int nhb) {
+  const float M = fmaxf(a.m, b.m);
+  if (M == -INFINITY) return;
+  const float e1 = exp2f(a.m - M), e2 = exp2f(b.m - M);
+  a.l = a.l * e1 + b.l * e2;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = s * 32 + grp * 8 + i;
-          t[i] = (cvalid && s < nkstep && k < hd) ? Q[qbase + k] : uint16_t(0);
-        }
-        qb[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<v4i*>(t));
+  for (int hb = 0; hb < HDMAX / 16; ++hb)
+    if (hb < nhb) a.o[hb] = a.o[hb] * e1 + b.o[hb] * e2;
+  a.m = M;
+}
+
+template <int PA>
+struct QFrag {
+  v8bf b[2];
+  float f[HDMAX / 4];
+};
+
+template <int PA>
+__device__ __forceinline__ void load_q(QFrag<PA>& q, const AttnArgs& a, const AttnCol& c,
+                                       int grp) {
+  const int hd = a.hd;
+  const long long qbase = ((long long)c.row * a.Hq + c.head) * hd;
+  if constexpr (PA == P_BF16) {
+    const uint16_t* Q = static_cast<const uint16_t*>(a.q);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      alignas(16) uint16_t t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = s * 32 + grp * 8 + i;
+        t[i] = (c.valid && k < hd) ? Q[qbase + k] : uint16_t(0);
       }
-    } else {
-      const float* Q = static_cast<const float*>(a.q);
+      q.b[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<v4i*>(t));
+    }
+  } else {
+    // step s, lane group g: hd entry 16 g + s (the same mapping is used for K)
+    const float* Q = static_cast<const float*>(a.q);
 #pragma unroll
-      for (int s = 0; s < HDMAX / 4; ++s) {
-        const int k = s * 4 + grp;
-        qf[s] = (cvalid && s < nkstep) ? Q[qbase + k] : 0.f;
-      }
+    for (int s = 0; s < HDMAX / 4; ++s) {
+      const int k = 16 * grp + s;
+      q.f[s] = (c.valid && k < hd) ? Q[qbase + k] : 0.f;
     }
   }
+}
 
-  for (int ci = wave; ci < nch; ci += NW) {
-    const int kc0 = (ch0 + ci) * KCH;
-    const int b0 = max(kc0, kmin) / 16, b1 = min(kc0 + KCH - 1, kmax) / 16;
-    float m = -INFINITY, l = 0.f;
-    v4f acc[HDMAX / 16];
+// Softmax of one chunk's masked scores st (in place: scores -> probabilities); returns (m, l).
+__device__ __forceinline__ void chunk_softmax(v4f (&st)[4], const AttnArgs& a, const AttnCol& c,
+                                              int key0, int grp, float& m, float& l) {
+  float mx = -INFINITY;
 #pragma unroll
-    for (int hb = 0; hb < HDMAX / 16; ++hb) acc[hb] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int kb = b0; kb <= b1; ++kb) {
-      const int key0 = kb * 16;
-      // S^T block: rows = keys key0 + l%16 (A operand), columns = (query, head)
-      v4f st = {0.f, 0.f, 0.f, 0.f};
-      {
-        const long long ks = sbase + (long long)((key0 + col) % a.ring) * hd;
-        if constexpr (PA == P_BF16) {
-          const uint16_t* Kc = static_cast<const uint16_t*>(a.k_cache);
+  for (int b = 0; b < 4; ++b)
 #pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            if (s < nkstep) {
-              v4i raw = {0, 0, 0, 0};
-              const int k = s * 32 + grp * 8;
-              if (k < hd) raw = *reinterpret_cast<const v4i*>(Kc + ks + k);
-              st = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, raw), qb[s],
-                                                           st, 0, 0, 0);
-            }
-          }
-        } else {
-          const float* Kc = static_cast<const float*>(a.k_cache);
+    for (int j = 0; j < 4; ++j) {
+      const int key = key0 + b * 16 + grp * 4 + j;
+      const bool ok = c.valid && key >= c.cs && key <= c.pos;
+      st[b][j] = ok ? st[b][j] * a.scale_log2 : -INFINITY;
+      mx = fmaxf(mx, st[b][j]);
+    }
+  mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+  mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+  float ls = 0.f;
 #pragma unroll
-          for (int s = 0; s < HDMAX / 4; ++s)
-            if (s < nkstep)
-              st = __builtin_amdgcn_mfma_f32_16x16x4f32(Kc[ks + s * 4 + grp], qf[s], st, 0, 0, 0);
-        }
+  for (int b = 0; b < 4; ++b) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st[b][j] = mx == -INFINITY ? 0.f : exp2f(st[b][j] - mx);
+    ls += (st[b][0] + st[b][1]) + (st[b][2] + st[b][3]);
+  }
+  ls += __shfl_xor(ls, 16, 64);
+  ls += __shfl_xor(ls, 32, 64);
+  m = mx;
+  l = ls;
+}
+
+// One chunk partial for the 16 columns of this wave.
+template <int PA>
+__device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const AttnItem& it,
+                                                    const AttnCol& c, const QFrag<PA>& q,
+                                                    int chunk, int col, int grp) {
+  const int hd = a.hd, nhb = hd / 16;
+  const long long sbase = (long long)it.stream * a.kv_stride + (long long)it.kvh * a.ring * hd;
+  const int key0 = chunk * KCH;
+  v4f st[4];
+  ChunkState r;
+#pragma unroll
+  for (int hb = 0; hb < HDMAX / 16; ++hb) r.o[hb] = v4f{0.f, 0.f, 0.f, 0.f};
+  if constexpr (PA == P_BF16) {
+    const uint16_t* Kc = static_cast<const uint16_t*>(a.k_cache);
+    const uint16_t* Vt = static_cast<const uint16_t*>(a.vt_cache);
+    // K and V^T fragments of the 4 blocks, all loads in flight together
+    v4i kf[4][2];
+    v4s vf[4][HDMAX / 16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long long ks = sbase + (long long)((key0 + b * 16 + col) % a.ring) * hd;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int k = s * 32 + grp * 8;
+        kf[b][s] = k < hd ? *reinterpret_cast<const v4i*>(Kc + ks + k) : v4i{0, 0, 0, 0};
       }
-      // mask and scale; lane holds keys key0 + 4 grp + j of column col
-      float p[4];
-      float mx = -INFINITY;
+      const int slot = (key0 + b * 16 + grp * 4) % a.ring;
+#pragma unroll
+      for (int hb = 0; hb < HDMAX / 16; ++hb)
+        vf[b][hb] = hb < nhb ? *reinterpret_cast<const v4s*>(
+                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + slot)
+                             : v4s{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      st[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        if (s * 32 < hd)
+          st[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, kf[b][s]),
+                                                          q.b[s], st[b], 0, 0, 0);
+    }
+    chunk_softmax(st, a, c, key0, grp, r.m, r.l);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      v4s pb;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pb[j] = short(f2bf(st[b][j]));
+#pragma unroll
+      for (int hb = 0; hb < HDMAX / 16; ++hb)
+        if (hb < nhb) r.o[hb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vf[b][hb], pb, r.o[hb], 0, 0, 0);
+    }
+  } else {
+    const float* Kc = static_cast<const float*>(a.k_cache);
+    const float* Vt = static_cast<const float*>(a.vt_cache);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long long ks = sbase + (long long)((key0 + b * 16 + col) % a.ring) * hd;
+      float kf[HDMAX / 4];
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd) {
+        const int k = 16 * grp + 4 * qd;
+        const v4f v = k < hd ? *reinterpret_cast<const v4f*>(Kc + ks + k) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) kf[4 * qd + e] = v[e];
+      }
+      st[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < HDMAX / 4; ++s)
+        st[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kf[s], q.f[s], st[b], 0, 0, 0);
+    }
+    // V^T fragments requested before the softmax so their latency overlaps it
+    v4f vf[4][HDMAX / 16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int slot = (key0 + b * 16 + grp * 4) % a.ring;
+#pragma unroll
+      for (int hb = 0; hb < HDMAX / 16; ++hb)
+        vf[b][hb] = hb < nhb ? *reinterpret_cast<const v4f*>(
+                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + slot)
+                             : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    chunk_softmax(st, a, c, key0, grp, r.m, r.l);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int hb = 0; hb < HDMAX / 16; ++hb)
+        if (hb < nhb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            r.o[hb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[b][hb][j], st[b][j], r.o[hb], 0, 0, 0);
+  }
+  return r;
+}
+
+__device__ __forceinline__ AttnCol attn_col(const AttnArgs& a, const AttnItem& it, int col) {
+  const int g = a.Hq / a.Hk;
+  const int cc = it.c0 + col;
+  AttnCol c;
+  c.valid = col < it.ncols;
+  const int qo = cc / g;
+  c.head = it.kvh * g + cc % g;
+  c.pos = it.pos_base + qo;
+  c.row = it.row_base + qo;
+  c.cs = window_start(c.pos, a.ctx_len, a.slide);
+  return c;
+}
+
+// absolute chunk range [c_lo, c_hi] of an item
+__device__ __forceinline__ void item_chunks(const AttnArgs& a, const AttnItem& it, int& c_lo,
+                                            int& c_hi) {
+  const int g = a.Hq / a.Hk;
+  const int kmin = window_start(it.pos_base + it.c0 / g, a.ctx_len, a.slide);
+  const int kmax = it.pos_base + (it.c0 + it.ncols - 1) / g;
+  c_lo = kmin / KCH;
+  c_hi = kmax / KCH;
+}
+
+template <int PO>
+__device__ __forceinline__ float attn_store(const AttnArgs& a, const AttnItem& it,
+                                            const ChunkState& s, int col, int grp) {
+  const int g = a.Hq / a.Hk, hd = a.hd, nhb = hd / 16;
+  float omax = 0.f;
+  if (col >= it.ncols) return omax;
+  const int cc = it.c0 + col;
+  const long long orow = it.row_base + cc / g;
+  const int oh = it.kvh * g + cc % g;
+  const float oinv = (PO == P_FP8) ? 1.0f / a.out_scale : 1.0f;
+#pragma unroll
+  for (int hb = 0; hb < HDMAX / 16; ++hb)
+    if (hb < nhb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int key = key0 + grp * 4 + j;
-        const bool ok = cvalid && key >= cs && key <= pos;
-        p[j] = ok ? st[j] * a.scale_log2 : -INFINITY;
-        mx = fmaxf(mx, p[j]);
+        const int d = hb * 16 + grp * 4 + j;
+        const float o = s.o[hb][j] / s.l;
+        const long long idx = orow * ((long long)a.Hq * hd) + (long long)oh * hd + d;
+        omax = fmaxf(omax, fabsf(o));
+        if constexpr (PO == P_F32)
+          PT<P_F32>::store(a.out, idx, o, 1.f);
+        else if constexpr (PO == P_BF16)
+          PT<P_BF16>::store(a.out, idx, o, 1.f);
+        else
+          PT<P_FP8>::store(a.out, idx, o, oinv);
       }
-      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-      const float mn = fmaxf(m, mx);
-      float alpha;
-      if (mn == -INFINITY) {
-        alpha = 1.f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) p[j] = 0.f;
-      } else {
-        alpha = exp2f(m - mn);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) p[j] = exp2f(p[j] - mn);
-      }
-      float rs = (p[0] + p[1]) + (p[2] + p[3]);
-      rs += __shfl_xor(rs, 16, 64);
-      rs += __shfl_xor(rs, 32, 64);
-      l = l * alpha + rs;
-      m = mn;
-#pragma unroll
-      for (int hb = 0; hb < HDMAX / 16; ++hb) acc[hb] *= alpha;
-      // O^T += V^T P^T; A = V^T rows (hd), k = keys key0 + 4 grp + j
-      const int slot = (key0 + grp * 4) % a.ring;
-      if constexpr (PA == P_BF16) {
-        const uint16_t* Vt = static_cast<const uint16_t*>(a.vt_cache);
-        v4s pb;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) pb[j] = short(f2bf(p[j]));
-#pragma unroll
-        for (int hb = 0; hb < HDMAX / 16; ++hb)
-          if (hb < nhb) {
-            const v4s vv = *reinterpret_cast<const v4s*>(
-                Vt + sbase + (long long)(hb * 16 + col) * a.ring + slot);
-            acc[hb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vv, pb, acc[hb], 0, 0, 0);
-          }
-      } else {
-        const float* Vt = static_cast<const float*>(a.vt_cache);
-#pragma unroll
-        for (int hb = 0; hb < HDMAX / 16; ++hb)
-          if (hb < nhb) {
-            const float* vp = Vt + sbase + (long long)(hb * 16 + col) * a.ring + slot;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              acc[hb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vp[j], p[j], acc[hb], 0, 0, 0);
-          }
-      }
-    }
-    // chunk partial: lane holds o[hd = hb*16 + 4 grp + j][column col]
+  return omax;
+}
+
+// Many items (prefill): one wave per item; chunks folded per group, groups folded in order.
+template <int PA, int PO>
+__global__ __launch_bounds__(256) void attention_seq_kernel(const AttnArgs a) {
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= a.n_items) return;
+  const AttnItem it = a.items[item];
+  const AttnCol c = attn_col(a, it, col);
+  const int nhb = a.hd / 16;
+  QFrag<PA> q;
+  load_q<PA>(q, a, c, grp);
+  int c_lo, c_hi;
+  item_chunks(a, it, c_lo, c_hi);
+  ChunkState run, gs;
+  state_empty(run);
+  for (int g0 = (c_lo / GCH) * GCH; g0 <= c_hi; g0 += GCH) {
+    state_empty(gs);
+    for (int ch = max(g0, c_lo); ch <= min(g0 + GCH - 1, c_hi); ++ch)
+      fold(gs, chunk_partial<PA>(a, it, c, q, ch, col, grp), nhb);
+    fold(run, gs, nhb);
+  }
+  float omax = attn_store<PO>(a, it, run, col, grp);
+  if (a.out_amax) {
+    omax = wave_max_f(omax);
+    if (lane == 0) atomic_max_abs(a.out_amax, omax);
+  }
+}
+
+// Few items (decode): one workgroup per (item, group); wave w computes chunk group*16 + w, wave 0
+// folds the group's partials in order and writes the group state.
+template <int PA>
+__global__ __launch_bounds__(64 * DEC_WAVES) void attention_group_kernel(const AttnArgs a) {
+  __shared__ float pm[DEC_WAVES][16], pl[DEC_WAVES][16];
+  __shared__ float po[DEC_WAVES][HDMAX / 16][4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int item = blockIdx.x, gi = blockIdx.y;
+  const AttnItem it = a.items[item];
+  const AttnCol c = attn_col(a, it, col);
+  const int nhb = a.hd / 16;
+  int c_lo, c_hi;
+  item_chunks(a, it, c_lo, c_hi);
+  const int g0 = (c_lo / GCH + gi) * GCH;
+  const int ch = g0 + wave;
+  const bool active = ch >= c_lo && ch <= c_hi;
+  if (active) {
+    QFrag<PA> q;
+    load_q<PA>(q, a, c, grp);
+    const ChunkState p = chunk_partial<PA>(a, it, c, q, ch, col, grp);
     if (grp == 0) {
-      pm[ci][col] = m;
-      pl[ci][col] = l;
+      pm[wave][col] = p.m;
+      pl[wave][col] = p.l;
     }
 #pragma unroll
     for (int hb = 0; hb < HDMAX / 16; ++hb)
       if (hb < nhb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) po[ci][col][hb * 16 + grp * 4 + j] = acc[hb][j];
+        for (int j = 0; j < 4; ++j) po[wave][hb][j][lane] = p.o[hb][j];
   }
   __syncthreads();
-  // combine the chunks of each column in increasing order
-  const float oinv = (PO == P_FP8) ? 1.0f / a.out_scale : 1.0f;
-  float omax = 0.f;
-  for (int t = threadIdx.x; t < 16 * hd; t += 64 * NW) {
-    const int c = t / hd, d = t % hd;
-    if (c >= it.ncols) continue;
-    float M = -INFINITY;
-    for (int k = 0; k < nch; ++k) M = fmaxf(M, pm[k][c]);
-    float Lsum = 0.f, o = 0.f;
-    for (int k = 0; k < nch; ++k) {
-      const float e = exp2f(pm[k][c] - M);
-      Lsum += pl[k][c] * e;
-      o += po[k][c][d] * e;
-    }
-    o = o / Lsum;
-    const int ccc = it.c0 + c;
-    const long long orow = it.row_base + ccc / g;
-    const int oh = it.kvh * g + ccc % g;
-    const long long idx = orow * ((long long)a.Hq * hd) + (long long)oh * hd + d;
-    omax = fmaxf(omax, fabsf(o));
-    if constexpr (PO == P_F32)
-      PT<P_F32>::store(a.out, idx, o, 1.f);
-    else if constexpr (PO == P_BF16)
-      PT<P_BF16>::store(a.out, idx, o, 1.f);
-    else
-      PT<P_FP8>::store(a.out, idx, o, oinv);
+  if (wave != 0) return;
+  ChunkState gs;
+  state_empty(gs);
+  for (int w = 0; w < DEC_WAVES; ++w) {
+    if (!(g0 + w >= c_lo && g0 + w <= c_hi)) continue;
+    ChunkState p;
+    p.m = pm[w][col];
+    p.l = pl[w][col];
+#pragma unroll
+    for (int hb = 0; hb < HDMAX / 16; ++hb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p.o[hb][j] = hb < nhb ? po[w][hb][j][lane] : 0.f;
+    fold(gs, p, nhb);
   }
+  // group state: [item][gi][lane][2 + 16]
+  float* dst = a.ws + ((long long)item * MAXG + gi) * 64 * 18 + lane * 18;
+  dst[0] = gs.m;
+  dst[1] = gs.l;
+#pragma unroll
+  for (int hb = 0; hb < HDMAX / 16; ++hb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[2 + hb * 4 + j] = gs.o[hb][j];
+}
+
+template <int PO>
+__global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a, int ngroups) {
+  const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
+  const int item = blockIdx.x;
+  const AttnItem it = a.items[item];
+  const int nhb = a.hd / 16;
+  int c_lo, c_hi;
+  item_chunks(a, it, c_lo, c_hi);
+  const int ng = c_hi / GCH - c_lo / GCH + 1;
+  ChunkState run;
+  state_empty(run);
+  for (int gi = 0; gi < ng && gi < ngroups; ++gi) {
+    const float* src = a.ws + ((long long)item * MAXG + gi) * 64 * 18 + lane * 18;
+    ChunkState p;
+    p.m = src[0];
+    p.l = src[1];
+#pragma unroll
+    for (int hb = 0; hb < HDMAX / 16; ++hb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p.o[hb][j] = src[2 + hb * 4 + j];
+    fold(run, p, nhb);
+  }
+  float omax = attn_store<PO>(a, it, run, col, grp);
   if (a.out_amax) {
     omax = wave_max_f(omax);
     if (lane == 0) atomic_max_abs(a.out_amax, omax);
@@ -556,12 +1004,16 @@ __global__ __launch_bounds__(64 * NW) void attention_kernel(const AttnArgs a) {
 
 // ---- small kernels ------------------------------------------------------------------------
 
+// x[r] = E[tok]; one wave per row, which also writes the row's inverse RMS (row_inv_rms order).
 __global__ void embed_kernel(const float* __restrict__ E, const RowMeta* __restrict__ rows, int n,
-                             int d, float* __restrict__ x) {
+                             int d, float* __restrict__ x, float* __restrict__ inv, float eps) {
   const int r = blockIdx.x;
   if (r >= n) return;
+  const int lane = threadIdx.x;
   const long long t = rows[r].tok;
-  for (int k = threadIdx.x; k < d; k += blockDim.x) x[(long long)r * d + k] = E[t * d + k];
+  for (int k = lane; k < d; k += 64) x[(long long)r * d + k] = E[t * d + k];
+  const float v = row_inv_rms(E + t * d, d, eps, lane);
+  if (inv && lane == 0) inv[r] = v;
 }
 
 template <int P>
@@ -582,15 +1034,73 @@ static void gemm_go(const GemmArgs& a, hipStream_t s) {
                      a);
 }
 
+constexpr size_t kSplitLdsMax = 144 * 1024;  // of the 160 KiB LDS of a gfx950 CU
+
+template <int P, int AM, int EPI, int MB>
+static void launch_split(dim3 grid, dim3 block, size_t lds, const GemmArgs& a, hipStream_t s) {
+  static bool raised = false;  // allow more than the default 64 KiB of dynamic LDS, once
+  if (!raised) {
+    NC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_split_kernel<P, AM, EPI, MB>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(kSplitLdsMax)));
+    raised = true;
+  }
+  hipLaunchKernelGGL((gemm_split_kernel<P, AM, EPI, MB>), grid, block, lds, s, a);
+}
+
 template <int P, int AM, int EPI>
-static void gemm_shape(const GemmArgs& a, bool small_m, hipStream_t s) {
+static void gemm_split(const GemmArgs& a, hipStream_t s) {
+  const int S = (a.K + KP - 1) / KP;
+  const int nblk = (a.N + 15) / 16;
+  int ngroups, gsize;
+  if (EPI == E_GLU) {
+    gsize = 2;
+    ngroups = nblk / 2;
+  } else if (EPI == E_QKV && a.hd > 16) {
+    gsize = 2;
+    ngroups = nblk / 2;
+  } else {
+    gsize = 1;
+    ngroups = nblk;
+  }
+  const int mb = (a.M + 15) / 16;
+  const int items = gsize * S;
+  const int waves = items < SPLIT_WAVES ? items : SPLIT_WAVES;
+  const size_t lds = (size_t(items) * mb * 256 + mb * 16) * sizeof(float);
+  const dim3 grid(ngroups), block(64 * waves);
+  switch (mb) {
+    case 1: launch_split<P, AM, EPI, 1>(grid, block, lds, a, s); break;
+    case 2: launch_split<P, AM, EPI, 2>(grid, block, lds, a, s); break;
+    case 3: launch_split<P, AM, EPI, 3>(grid, block, lds, a, s); break;
+    default: launch_split<P, AM, EPI, 4>(grid, block, lds, a, s); break;
+  }
+}
+
+static bool split_fits(const GemmArgs& a, int epi) {
+  const int S = (a.K + KP - 1) / KP;
+  const int gsize = (epi == E_GLU || (epi == E_QKV && a.hd > 16)) ? 2 : 1;
+  const int mb = (a.M + 15) / 16;
+  return (size_t(gsize) * S * mb * 256 + mb * 16) * sizeof(float) <= kSplitLdsMax;
+}
+
+void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s) {
+  if (a.M <= 0) return;
+  hipLaunchKernelGGL(row_rms_kernel, dim3((a.M + 3) / 4), dim3(256), 0, s, a, inv);
+  NC_HIP(hipGetLastError());
+}
+
+template <int P, int AM, int EPI>
+static void gemm_shape(const GemmArgs& a, hipStream_t s) {
+  // few rows: spread K over waves; lm_head-sized N with more rows: the tile kernel has enough
+  // workgroups by itself
+  if (a.M <= 64 && split_fits(a, EPI) && (a.M <= 16 || (long long)a.N * a.K <= (4ll << 20)))
+    return gemm_split<P, AM, EPI>(a, s);
   if constexpr (EPI == E_GLU) {
-    if (small_m)
+    if (a.M <= 64)
       gemm_go<P, AM, EPI, 16, 32, 1, 2>(a, s);
     else
       gemm_go<P, AM, EPI, 32, 32, 2, 2>(a, s);
   } else {
-    if (small_m)
+    if (a.M <= 64)
       gemm_go<P, AM, EPI, 16, 16, 1, 4>(a, s);
     else
       gemm_go<P, AM, EPI, 32, 32, 2, 2>(a, s);
@@ -598,61 +1108,83 @@ static void gemm_shape(const GemmArgs& a, bool small_m, hipStream_t s) {
 }
 
 template <int P>
-static void gemm_prec(int amode, int epi, const GemmArgs& a, bool small_m, hipStream_t s) {
+static void gemm_prec(int amode, int epi, const GemmArgs& a, hipStream_t s) {
   if (amode == A_NORM) {
     switch (epi) {
-      case E_STORE: return gemm_shape<P, A_NORM, E_STORE>(a, small_m, s);
-      case E_GLU: return gemm_shape<P, A_NORM, E_GLU>(a, small_m, s);
-      case E_QKV: return gemm_shape<P, A_NORM, E_QKV>(a, small_m, s);
+      case E_STORE: return gemm_shape<P, A_NORM, E_STORE>(a, s);
+      case E_GLU: return gemm_shape<P, A_NORM, E_GLU>(a, s);
+      case E_QKV: return gemm_shape<P, A_NORM, E_QKV>(a, s);
       default: break;
     }
   } else if (epi == E_RESID) {
-    return gemm_shape<P, A_DIRECT, E_RESID>(a, small_m, s);
+    return gemm_shape<P, A_DIRECT, E_RESID>(a, s);
   }
   fail(NC_E_INVALID, "unsupported GEMM variant");
 }
 
-void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, bool small_m, hipStream_t s) {
+void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s) {
   if (a.M <= 0) return;
   NC_CHECK(a.K % 16 == 0, NC_E_INVALID, "GEMM K must be a multiple of 16");
   if (epi == E_QKV) NC_CHECK(64 % a.hd == 0, NC_E_INVALID, "head_dim must divide 64");
   if (epi == E_GLU) NC_CHECK(a.N % 32 == 0, NC_E_INVALID, "d_ffn must be a multiple of 16");
   if (prec == P_F32)
-    gemm_prec<P_F32>(amode, epi, a, small_m, s);
+    gemm_prec<P_F32>(amode, epi, a, s);
   else if (prec == P_BF16)
-    gemm_prec<P_BF16>(amode, epi, a, small_m, s);
+    gemm_prec<P_BF16>(amode, epi, a, s);
   else
-    gemm_prec<P_FP8>(amode, epi, a, small_m, s);
+    gemm_prec<P_FP8>(amode, epi, a, s);
   NC_HIP(hipGetLastError());
 }
 
-template <int PA, int PO>
-static void attn_go(const AttnArgs& a, int waves, hipStream_t s) {
-  if (waves >= 8)
-    hipLaunchKernelGGL((attention_kernel<PA, PO, 8>), dim3(a.n_items), dim3(512), 0, s, a);
-  else
-    hipLaunchKernelGGL((attention_kernel<PA, PO, 4>), dim3(a.n_items), dim3(256), 0, s, a);
+// Groups an item can span: its keys run from the window start of its first query to its last
+// query, at most ctx_len + 15 keys (a window holds at most ctx_len keys, an item at most 16
+// query positions), i.e. at most nch chunks at any alignment.
+static int attention_groups(int ctx_len) {
+  const int nch = (ctx_len + 15 + KCH - 1) / KCH + 1;
+  return (nch - 1 + GCH - 1) / GCH + 1;
 }
 
-void launch_attention(int prec_att, int prec_out, const AttnArgs& a, int waves, hipStream_t s) {
+template <int PA, int PO>
+static void attn_go(const AttnArgs& a, bool parallel, hipStream_t s) {
+  if (parallel) {
+    const int ng = attention_groups(a.ctx_len);
+    hipLaunchKernelGGL((attention_group_kernel<PA>), dim3(a.n_items, ng), dim3(64 * DEC_WAVES), 0,
+                       s, a);
+    hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64), 0, s, a, ng);
+  } else {
+    hipLaunchKernelGGL((attention_seq_kernel<PA, PO>), dim3((a.n_items + 3) / 4), dim3(256), 0, s,
+                       a);
+  }
+}
+
+size_t attention_ws_bytes(int n_items) { return size_t(n_items) * MAXG * 64 * 18 * sizeof(float); }
+
+// parallel: a workgroup per (item, 1,024-key group) and a fold kernel (few items, decode);
+// otherwise one wave per item (prefill).  Both produce the same bits.
+void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parallel,
+                      hipStream_t s) {
   if (a.n_items <= 0) return;
   NC_CHECK(a.hd % 16 == 0 && a.hd <= HDMAX, NC_E_INVALID, "head_dim must be 16..64, x16");
-  NC_CHECK((a.ctx_len + a.slide) <= (MAXCH - 1) * KCH, NC_E_INVALID, "window too large");
+  NC_CHECK(attention_groups(a.ctx_len) <= MAXG, NC_E_INVALID, "context window too large");
   NC_CHECK(a.ring % 16 == 0, NC_E_INVALID, "ring must be a multiple of 16");
+  if (parallel)
+    NC_CHECK(a.ws && a.ws_bytes >= attention_ws_bytes(a.n_items), NC_E_INVALID,
+             "attention workspace too small");
   if (prec_att == P_F32) {
     NC_CHECK(prec_out == P_F32, NC_E_INVALID, "fp32 attention feeds fp32 GEMMs");
-    attn_go<P_F32, P_F32>(a, waves, s);
+    attn_go<P_F32, P_F32>(a, parallel, s);
   } else if (prec_out == P_BF16) {
-    attn_go<P_BF16, P_BF16>(a, waves, s);
+    attn_go<P_BF16, P_BF16>(a, parallel, s);
   } else {
-    attn_go<P_BF16, P_FP8>(a, waves, s);
+    attn_go<P_BF16, P_FP8>(a, parallel, s);
   }
   NC_HIP(hipGetLastError());
 }
 
-void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, hipStream_t s) {
+void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, float* inv,
+                  float eps, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(embed_kernel, dim3(n), dim3(256), 0, s, E, rows, n, d, x);
+  hipLaunchKernelGGL(embed_kernel, dim3(n), dim3(64), 0, s, E, rows, n, d, x, inv, eps);
   NC_HIP(hipGetLastError());
 }
 

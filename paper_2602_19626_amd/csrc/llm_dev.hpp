@@ -42,6 +42,8 @@ struct GemmArgs {
   void* vt_cache;         // [stream][kvh][hd][R]
   long long kv_stride;    // elements per stream in k_cache / vt_cache (one layer)
   int Hq, Hk, hd, ring;
+  // split path (rows <= 64)
+  const float* inv;       // A_NORM: precomputed inverse RMS per A row (indexed like A), or null
 };
 
 // Attention work item: a block of up to 16 (query, head) columns of one stream and kv head.
@@ -69,11 +71,18 @@ struct AttnArgs {
   float* out_amax;      // optional calibration amax
   int Hq, Hk, hd, ring, ctx_len, slide;
   float scale_log2;     // log2(e) / sqrt(hd)
+  float* ws;            // group states of the parallel path
+  size_t ws_bytes;
 };
 
-void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, bool small_m, hipStream_t s);
-void launch_attention(int prec_att, int prec_out, const AttnArgs& a, int waves, hipStream_t s);
-void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, hipStream_t s);
+void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s);
+// inverse RMS (row_inv_rms) of rows a.A[a_rows[m]] into inv[a_rows[m]]
+void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s);
+void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parallel,
+                      hipStream_t s);
+size_t attention_ws_bytes(int n_items);
+void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, float* inv,
+                  float eps, hipStream_t s);
 void launch_convert(const float* src, void* dst, long long n, int prec, float inv_scale,
                     hipStream_t s);
 

@@ -88,6 +88,12 @@ struct nc_ctx {
   DevBuf<RowMeta> rowsd;
   DevBuf<AttnItem> itemsd;
   DevBuf<int32_t> lastrow;  // per stream: row of its last position in the latest pass
+  DevBuf<float> xinv;       // inverse RMS of each pass row's residual
+  DevBuf<float> aws;        // attention group states (decode path)
+  DevBuf<float> hinv;       // inverse RMS of each stream's newest residual (hlast)
+  DevBuf<uint8_t> dstage;   // per-step staged inputs
+  void* spin = nullptr;     // pinned host side of the stage
+  size_t spin_bytes = 0;
   // step buffers
   DevBuf<float> z;
   DevBuf<int32_t> steprows, arows;
@@ -107,6 +113,12 @@ struct nc_ctx {
   std::vector<int> appended;                // x positions in the KV cache per stream
   nc_stats stats{};
   VocabParams vp{};
+  // measurement: events around launches of one kernel class
+  int prof_class = -1;
+  nc_kstat prof{};
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_busy;
+  hipEvent_t ev_open = nullptr;
 
   ~nc_ctx();
 };
@@ -115,7 +127,7 @@ nc_ctx::~nc_ctx() {
   if (dev >= 0) (void)hipSetDevice(dev);
   if (st) (void)hipStreamSynchronize(st);
   for (void* p : allocs) (void)hipFree(p);
-  DevBuf<float>* fb[] = {&amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
+  DevBuf<float>* fb[] = {&aws, &xinv, &hinv, &amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
                          &dbgp, &dbgpt};
   for (auto* q : fb) q->release();
   DevBuf<int32_t>* ib[] = {&uni, &nseen, &hist, &ncommit, &moded, &next_ctx, &keys, &kidx,
@@ -137,6 +149,13 @@ nc_ctx::~nc_ctx() {
   outc.release();
   sout.release();
   if (pin) (void)hipHostFree(pin);
+  if (spin) (void)hipHostFree(spin);
+  dstage.release();
+  for (auto e : ev_free) (void)hipEventDestroy(e);
+  for (auto& pr : ev_busy) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
   if (st) (void)hipStreamDestroy(st);
 }
 
@@ -159,13 +178,69 @@ void* pinned(nc_ctx* c, size_t bytes) {
   return c->pin;
 }
 
+hipEvent_t take_event(nc_ctx* c) {
+  if (c->ev_free.empty()) {
+    hipEvent_t e;
+    NC_HIP(hipEventCreate(&e));
+    return e;
+  }
+  hipEvent_t e = c->ev_free.back();
+  c->ev_free.pop_back();
+  return e;
+}
+
+// Collect the elapsed time of recorded event pairs (the stream has been synchronised).
+void prof_flush(nc_ctx* c) {
+  for (auto& pr : c->ev_busy) {
+    float ms = 0.f;
+    NC_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    c->prof.ms += ms;
+    c->ev_free.push_back(pr.first);
+    c->ev_free.push_back(pr.second);
+  }
+  c->ev_busy.clear();
+}
+
+void sync(nc_ctx* c) {
+  NC_HIP(hipStreamSynchronize(c->st));
+  prof_flush(c);
+}
+
+// Bracket the launches of one kernel class; bytes / flops are the launch's algorithmic work.
+void prof_begin(nc_ctx* c, int cls) {
+  if (cls != c->prof_class) return;
+  c->ev_open = take_event(c);
+  NC_HIP(hipEventRecord(c->ev_open, c->st));
+}
+void prof_end(nc_ctx* c, int cls, double bytes, double flops) {
+  if (cls != c->prof_class) return;
+  hipEvent_t e = take_event(c);
+  NC_HIP(hipEventRecord(e, c->st));
+  c->ev_busy.emplace_back(c->ev_open, e);
+  c->prof.launches += 1;
+  c->prof.bytes += bytes;
+  c->prof.flops += flops;
+  if (c->ev_busy.size() > 4096) sync(c);
+}
+
+double gemm_bytes(const GemmArgs& a, int amode, int epi, int prec, int att) {
+  const double es = double(prec_bytes(prec));
+  double b = double(a.N) * a.K * es;                                    // weights
+  b += double(a.M) * a.K * (amode == A_NORM ? 4.0 : es);                // activations
+  if (epi == E_STORE) b += double(a.M) * a.N * 4.0;                     // logits
+  if (epi == E_RESID) b += double(a.M) * a.N * 8.0;                     // residual read + write
+  if (epi == E_GLU) b += double(a.M) * (a.N / 2) * es;                  // gated activation
+  if (epi == E_QKV) b += double(a.M) * a.N * double(prec_bytes(att));   // q, k, v
+  return b;
+}
+
 template <class T>
 void h2d(nc_ctx* c, T* dst, const T* src, size_t n) {
   if (!n) return;
   void* p = pinned(c, n * sizeof(T));
   std::memcpy(p, src, n * sizeof(T));
   NC_HIP(hipMemcpyAsync(dst, p, n * sizeof(T), hipMemcpyHostToDevice, c->st));
-  NC_HIP(hipStreamSynchronize(c->st));
+  sync(c);
 }
 
 template <class T>
@@ -173,7 +248,7 @@ void d2h(nc_ctx* c, T* dst, const T* src, size_t n) {
   if (!n) return;
   void* p = pinned(c, n * sizeof(T));
   NC_HIP(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyDeviceToHost, c->st));
-  NC_HIP(hipStreamSynchronize(c->st));
+  sync(c);
   std::memcpy(dst, p, n * sizeof(T));
 }
 
@@ -203,7 +278,7 @@ void* upload_weight(nc_ctx* c, const float* host, size_t n, float* scale_out, fl
   }
   void* wp = dmalloc(c, n * prec_bytes(c->prec));
   launch_convert(w32, wp, (long long)n, c->prec, inv, c->st);
-  NC_HIP(hipStreamSynchronize(c->st));
+  sync(c);
   return wp;
 }
 
@@ -228,6 +303,7 @@ void ensure_rows(nc_ctx* c, int rows) {
   if (rows <= c->rows_alloc) return;
   const int r = std::max(rows, 64);
   c->x.alloc((size_t)r * c->d);
+  c->xinv.alloc(r);
   // sized for float32 so that the calibration pass (float32 GEMMs) fits in any precision
   c->qb.alloc((size_t)r * c->hq * c->hd * 4);
   c->ob.alloc((size_t)r * c->hq * c->hd * 4);
@@ -256,47 +332,118 @@ struct BodyOpts {
   bool calib = false;  // FP32 weights with amax recording (FP8 calibration)
 };
 
-// Appends rows (stream, pos, token) to the KV caches and leaves each row's final residual in x.
-// Rows of one stream must be consecutive positions spanning fewer than `slide` positions.
-void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
-  const int n = int(rows.size());
-  if (!n) return;
-  ensure_rows(c, n);
-  // attention items: per stream run of consecutive rows, per kv head, 16 columns each
+// Small per-step inputs gathered on the host and uploaded with one copy.
+struct Stage {
+  std::vector<uint8_t> h;
+  size_t put(const void* p, size_t n) {
+    const size_t off = (h.size() + 255) & ~size_t(255);
+    h.resize(off + std::max<size_t>(n, 1));
+    if (n) std::memcpy(h.data() + off, p, n);
+    return off;
+  }
+};
+
+// One transformer pass: rows (stream, position, token), attention items, and which rows are the
+// newest of their stream (kept in hlast for the output layer).
+struct PassPlan {
+  std::vector<RowMeta> rows;
   std::vector<AttnItem> items;
+  std::vector<int32_t> last;  // n_last source rows, then n_last destination streams
+  double attn_bytes = 0, attn_flops = 0;
+  size_t off_rows = 0, off_items = 0, off_last = 0;
+};
+
+PassPlan plan_pass(nc_ctx* c, std::vector<RowMeta> rows, bool calib = false) {
+  PassPlan p;
+  p.rows = std::move(rows);
+  const std::vector<RowMeta>& R = p.rows;
+  const int n = int(R.size());
   const int g = c->hq / c->hk;
+  const int L = c->cfg.ctx_len, C = c->cfg.slide;
+  auto wstart = [&](int q) { return q < L ? 0 : C * (1 + (q - L) / C); };
+  const double esa = double(prec_bytes(calib ? P_F32 : c->att));
+  const double eso = double(prec_bytes(calib ? P_F32 : c->prec));
+  std::vector<int32_t> src, dst;
   for (int i = 0; i < n;) {
     int j = i;
-    while (j + 1 < n && rows[j + 1].stream == rows[i].stream && rows[j + 1].pos == rows[j].pos + 1)
-      ++j;
+    while (j + 1 < n && R[j + 1].stream == R[i].stream && R[j + 1].pos == R[j].pos + 1) ++j;
     const int nq = j - i + 1;
     for (int kvh = 0; kvh < c->hk; ++kvh)
       for (int c0 = 0; c0 < nq * g; c0 += 16) {
         AttnItem it{};
-        it.stream = rows[i].stream;
+        it.stream = R[i].stream;
         it.kvh = kvh;
         it.row_base = i;
-        it.pos_base = rows[i].pos;
+        it.pos_base = R[i].pos;
         it.c0 = c0;
         it.ncols = std::min(16, nq * g - c0);
-        items.push_back(it);
+        p.items.push_back(it);
+        // algorithmic work: the item's window keys/values read once, q in, o out
+        const int p0 = it.pos_base + it.c0 / g, p1 = it.pos_base + (it.c0 + it.ncols - 1) / g;
+        p.attn_bytes += double(p1 - wstart(p0) + 1) * c->hd * 2 * esa +
+                        it.ncols * double(c->hd) * (esa + eso);
+        for (int cc = 0; cc < it.ncols; ++cc) {
+          const int q = it.pos_base + (it.c0 + cc) / g;
+          p.attn_flops += 4.0 * double(q - wstart(q) + 1) * c->hd;
+        }
       }
+    src.push_back(j);
+    dst.push_back(R[j].stream);
     i = j + 1;
   }
-  if ((int)items.size() > (int)c->itemsd.n) c->itemsd.alloc(items.size());
-  {
-    const size_t b1 = n * sizeof(RowMeta), b2 = items.size() * sizeof(AttnItem);
-    uint8_t* p = static_cast<uint8_t*>(pinned(c, b1 + b2));
-    std::memcpy(p, rows.data(), b1);
-    std::memcpy(p + b1, items.data(), b2);
-    NC_HIP(hipMemcpyAsync(c->rowsd.p, p, b1, hipMemcpyHostToDevice, c->st));
-    NC_HIP(hipMemcpyAsync(c->itemsd.p, p + b1, b2, hipMemcpyHostToDevice, c->st));
-    NC_HIP(hipStreamSynchronize(c->st));
+  p.last = src;
+  p.last.insert(p.last.end(), dst.begin(), dst.end());
+  return p;
+}
+
+void stage_pass(Stage& s, PassPlan& p) {
+  p.off_rows = s.put(p.rows.data(), p.rows.size() * sizeof(RowMeta));
+  p.off_items = s.put(p.items.data(), p.items.size() * sizeof(AttnItem));
+  p.off_last = s.put(p.last.data(), p.last.size() * sizeof(int32_t));
+}
+
+// Upload the stage with one asynchronous copy; the step ends with a stream synchronisation
+// before the staging memory is written again.
+uint8_t* upload_stage(nc_ctx* c, const Stage& s) {
+  sync(c);  // earlier work may still read the device stage or the pinned copy
+  const size_t n = s.h.size();
+  if (n > c->spin_bytes) {
+    if (c->spin) NC_HIP(hipHostFree(c->spin));
+    c->spin = nullptr;
+    NC_HIP(hipHostMalloc(&c->spin, n * 2, hipHostMallocDefault));
+    c->spin_bytes = n * 2;
   }
-  const bool small = n <= 64;
+  c->dstage.alloc(std::max<size_t>(n, 256));
+  if (n) {
+    std::memcpy(c->spin, s.h.data(), n);
+    NC_HIP(hipMemcpyAsync(c->dstage.p, c->spin, n, hipMemcpyHostToDevice, c->st));
+  }
+  return c->dstage.p;
+}
+
+__global__ void copy_rows_kernel(const float* x, const float* xinv, const int32_t* src_rows,
+                                 const int32_t* dst_rows, int n, int d, float* out, float* oinv) {
+  const int r = blockIdx.x;
+  if (r >= n) return;
+  const long long s = src_rows[r], t = dst_rows[r];
+  for (int k = threadIdx.x; k < d; k += blockDim.x) out[t * d + k] = x[s * d + k];
+  if (threadIdx.x == 0) oinv[t] = xinv[s];
+}
+
+// Appends a planned pass to the KV caches; leaves each row's final residual in x and each
+// stream's newest row in hlast.  Rows of one stream are consecutive positions spanning fewer than
+// `slide` positions (the ring holds ctx_len + slide entries, so no needed key is overwritten).
+void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = {}) {
+  const int n = int(p.rows.size());
+  if (!n) return;
+  ensure_rows(c, n);
+  const RowMeta* drows = reinterpret_cast<const RowMeta*>(dstage + p.off_rows);
+  const AttnItem* ditems = reinterpret_cast<const AttnItem*>(dstage + p.off_items);
+  const int g = c->hq / c->hk;
+  (void)g;
   const int prec = o.calib ? P_F32 : c->prec;
   const int att = o.calib ? P_F32 : c->att;
-  launch_embed(c->E32, c->rowsd.p, n, c->d, c->x.p, c->st);
+  launch_embed(c->E32, drows, n, c->d, c->x.p, c->xinv.p, c->cfg.norm_eps, c->st);
   const long long layer_kv = (long long)c->S_alloc * c->kv_stride * prec_bytes(c->att);
   for (int l = 0; l < c->nl; ++l) {
     Layer& L = c->layers[l];
@@ -313,7 +460,7 @@ void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
     a.a_amax = am ? am + 0 : nullptr;
     a.W = o.calib ? (void*)L.Wqkv32 : L.Wqkv;
     a.w_scale = o.calib ? 1.f : L.sw_qkv;
-    a.rows = c->rowsd.p;
+    a.rows = drows;
     a.rope = c->rope.p;
     a.q_out = c->qb.p;
     a.k_cache = c->kc.p + l * layer_kv;
@@ -323,11 +470,13 @@ void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
     a.Hk = c->hk;
     a.hd = c->hd;
     a.ring = c->R;
-    launch_gemm(prec, A_NORM, E_QKV, a, small, c->st);
+    prof_begin(c, NC_K_QKV);
+    launch_gemm(prec, A_NORM, E_QKV, a, c->st);
+    prof_end(c, NC_K_QKV, gemm_bytes(a, A_NORM, E_QKV, prec, att), 2.0 * a.M * a.N * a.K);
     // attention
     AttnArgs t{};
-    t.items = c->itemsd.p;
-    t.n_items = int(items.size());
+    t.items = ditems;
+    t.n_items = int(p.items.size());
     t.q = c->qb.p;
     t.k_cache = a.k_cache;
     t.vt_cache = a.vt_cache;
@@ -342,7 +491,15 @@ void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
     t.ctx_len = c->cfg.ctx_len;
     t.slide = c->cfg.slide;
     t.scale_log2 = float(1.4426950408889634 / std::sqrt((double)c->hd));
-    launch_attention(att, prec, t, items.size() < 2048 ? 8 : 4, c->st);
+    prof_begin(c, NC_K_ATTN);
+    const bool par = p.items.size() < 1024;
+    if (par) {
+      c->aws.alloc(attention_ws_bytes(int(p.items.size())) / 4);
+      t.ws = c->aws.p;
+      t.ws_bytes = c->aws.n * 4;
+    }
+    launch_attention(att, prec, t, par, c->st);
+    prof_end(c, NC_K_ATTN, p.attn_bytes, p.attn_flops);
     // O projection + residual
     GemmArgs ob{};
     ob.M = n;
@@ -354,7 +511,9 @@ void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
     ob.w_scale = o.calib ? 1.f : L.sw_o;
     ob.out_f32 = c->x.p;
     ob.ldo = c->d;
-    launch_gemm(prec, A_DIRECT, E_RESID, ob, small, c->st);
+    prof_begin(c, NC_K_OPROJ);
+    launch_gemm(prec, A_DIRECT, E_RESID, ob, c->st);
+    prof_end(c, NC_K_OPROJ, gemm_bytes(ob, A_DIRECT, E_RESID, prec, att), 2.0 * n * ob.N * ob.K);
     // gate/up with SiLU
     GemmArgs gu{};
     gu.M = n;
@@ -370,7 +529,9 @@ void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
     gu.out_p = c->hb.p;
     gu.out_scale = L.sa_d;
     gu.out_amax = am ? am + 3 : nullptr;
-    launch_gemm(prec, A_NORM, E_GLU, gu, small, c->st);
+    prof_begin(c, NC_K_GATEUP);
+    launch_gemm(prec, A_NORM, E_GLU, gu, c->st);
+    prof_end(c, NC_K_GATEUP, gemm_bytes(gu, A_NORM, E_GLU, prec, att), 2.0 * n * gu.N * gu.K);
     // down projection + residual
     GemmArgs dn{};
     dn.M = n;
@@ -382,14 +543,30 @@ void run_body(nc_ctx* c, const std::vector<RowMeta>& rows, BodyOpts o = {}) {
     dn.w_scale = o.calib ? 1.f : L.sw_d;
     dn.out_f32 = c->x.p;
     dn.ldo = c->d;
-    launch_gemm(prec, A_DIRECT, E_RESID, dn, small, c->st);
+    prof_begin(c, NC_K_DOWN);
+    launch_gemm(prec, A_DIRECT, E_RESID, dn, c->st);
+    prof_end(c, NC_K_DOWN, gemm_bytes(dn, A_DIRECT, E_RESID, prec, att), 2.0 * n * dn.N * dn.K);
   }
+  const int nl = int(p.last.size() / 2);
+  const int32_t* dl = reinterpret_cast<const int32_t*>(dstage + p.off_last);
+  {
+    // inverse RMS of every final row, for the output layer (same arithmetic as the GEMMs)
+    GemmArgs r{};
+    r.M = n;
+    r.K = c->d;
+    r.A = c->x.p;
+    r.eps = c->cfg.norm_eps;
+    launch_row_rms(r, c->xinv.p, c->st);
+  }
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(nl), dim3(256), 0, c->st, c->x.p, c->xinv.p, dl,
+                     dl + nl, nl, c->d, c->hlast.p, c->hinv.p);
+  NC_HIP(hipGetLastError());
   c->stats.body_rows += n;
 }
 
 // z[m] = final_norm(A[a_rows[m]]) E^T for m < M.
-void run_lm_head(nc_ctx* c, const float* A, const int32_t* a_rows, int M, float* zout,
-                 bool calib = false) {
+void run_lm_head(nc_ctx* c, const float* A, const float* Ainv, const int32_t* a_rows, int M,
+                 float* zout, bool calib = false) {
   GemmArgs a{};
   a.M = M;
   a.N = c->V;
@@ -404,38 +581,17 @@ void run_lm_head(nc_ctx* c, const float* A, const int32_t* a_rows, int M, float*
   a.w_scale = calib ? 1.f : c->sw_lm;
   a.out_f32 = zout;
   a.ldo = c->V;
-  launch_gemm(calib ? P_F32 : c->prec, A_NORM, E_STORE, a, M <= 64, c->st);
+  a.inv = Ainv;
+  const int prec = calib ? P_F32 : c->prec;
+  prof_begin(c, NC_K_LMHEAD);
+  launch_gemm(prec, A_NORM, E_STORE, a, c->st);
+  prof_end(c, NC_K_LMHEAD, gemm_bytes(a, A_NORM, E_STORE, prec, c->att), 2.0 * M * a.N * a.K);
 }
 
-__global__ void copy_rows_kernel(const float* x, const int32_t* src_rows, const int32_t* dst_rows,
-                                 int n, int d, float* out) {
-  const int r = blockIdx.x;
-  if (r >= n) return;
-  const long long s = src_rows[r], t = dst_rows[r];
-  for (int k = threadIdx.x; k < d; k += blockDim.x) out[t * d + k] = x[s * d + k];
-}
-
-// After a pass, keep each stream's last residual row (its newest position) in hlast.
-void save_last_rows(nc_ctx* c, const std::vector<RowMeta>& rows) {
-  std::vector<int32_t> src, dst;
-  for (size_t i = 0; i < rows.size(); ++i)
-    if (i + 1 == rows.size() || rows[i + 1].stream != rows[i].stream) {
-      src.push_back(int32_t(i));
-      dst.push_back(rows[i].stream);
-    }
-  const int n = int(src.size());
-  c->lastrow.alloc(2 * n + 2);
-  std::vector<int32_t> both(src);
-  both.insert(both.end(), dst.begin(), dst.end());
-  h2d(c, c->lastrow.p, both.data(), both.size());
-  hipLaunchKernelGGL(copy_rows_kernel, dim3(n), dim3(256), 0, c->st, c->x.p, c->lastrow.p,
-                     c->lastrow.p + n, n, c->d, c->hlast.p);
-  NC_HIP(hipGetLastError());
-}
-
-// Append x positions [appended[s], upto] of each listed stream, in passes that never span a
-// slide boundary's worth of positions; the last pass holds every stream's newest position.
-void catch_up(nc_ctx* c, const std::vector<int>& streams, const std::vector<int>& upto) {
+// Plan the appends of x positions [appended[s], upto] of each listed stream, in passes of at most
+// `slide` positions per stream; the last pass holds every stream's newest position.
+std::vector<PassPlan> plan_catch_up(nc_ctx* c, const std::vector<int>& streams,
+                                    const std::vector<int>& upto) {
   const int C = c->cfg.slide;
   int npass = 0;
   std::vector<int> nch(streams.size());
@@ -444,22 +600,34 @@ void catch_up(nc_ctx* c, const std::vector<int>& streams, const std::vector<int>
     nch[k] = pend > 0 ? (pend + C - 1) / C : 0;
     npass = std::max(npass, nch[k]);
   }
-  for (int p = 0; p < npass; ++p) {
+  std::vector<PassPlan> plans;
+  for (int pi = 0; pi < npass; ++pi) {
     std::vector<RowMeta> rows;
     for (size_t k = 0; k < streams.size(); ++k) {
       const int s = streams[k];
-      const int ci = p - (npass - nch[k]);
+      const int ci = pi - (npass - nch[k]);
       if (ci < 0) continue;
       const int a = c->appended[s] + ci * C;
       const int e = std::min(upto[k], a + C - 1);
       for (int j = a; j <= e; ++j)
         rows.push_back(RowMeta{s, j, j == 0 ? kBOS : c->hhist[s][j - 1], 0});
     }
-    run_body(c, rows);
-    save_last_rows(c, rows);
+    plans.push_back(plan_pass(c, std::move(rows)));
   }
   for (size_t k = 0; k < streams.size(); ++k)
     c->appended[streams[k]] = std::max(c->appended[streams[k]], upto[k] + 1);
+  return plans;
+}
+
+// Single-stream catch-up (probe and commit calls): plan, upload, run.
+void catch_up_now(nc_ctx* c, int s, int upto) {
+  std::vector<PassPlan> plans = plan_catch_up(c, {s}, {upto});
+  if (plans.empty()) return;
+  Stage st;
+  for (auto& p : plans) stage_pass(st, p);
+  const uint8_t* d = upload_stage(c, st);
+  for (auto& p : plans) run_pass(c, p, d);
+  sync(c);
 }
 
 StreamState make_state(nc_ctx* c) {
@@ -512,6 +680,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
     c->Hd.alloc(Sa);
     c->pmaxd.alloc(Sa);
     c->hlast.alloc((size_t)Sa * c->d);
+    c->hinv.alloc(Sa);
     c->uni.alloc((size_t)Sa * V);
     c->nseen.alloc(Sa);
     c->hist.alloc((size_t)Sa * Ta);
@@ -547,6 +716,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
   NC_HIP(hipMemsetAsync(c->kc.p, 0, c->kc.n, c->st));
   NC_HIP(hipMemsetAsync(c->vc.p, 0, c->vc.n, c->st));
   NC_HIP(hipMemsetAsync(c->hlast.p, 0, c->hlast.n * 4, c->st));
+  NC_HIP(hipMemsetAsync(c->hinv.p, 0, c->hinv.n * 4, c->st));
   launch_state_reset(c->vp, c->S, c->S_alloc, c->cfg.mix_w_llm, c->st);
   ensure_step(c, std::max(n, 1));
   if (ngram_on(c)) {
@@ -555,7 +725,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
     h2d(c, c->steprows.p, ids.data(), ids.size());
     launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
   }
-  NC_HIP(hipStreamSynchronize(c->st));
+  sync(c);
   c->hhist.assign(n, {});
   c->appended.assign(n, 0);
 }
@@ -577,10 +747,17 @@ StepArgs step_args(nc_ctx* c, int B, bool decode) {
 
 // One coding step for rows steprows[0..B): updates and next-position prediction included.
 void vocab_commit_step(nc_ctx* c, const StepArgs& A) {
+  // per row: z and b read by the logsumexp, count and scan passes, p_ng by two, b written
+  const double V = c->V;
+  prof_begin(c, NC_K_VOCAB);
   launch_vocab_step(c->vp, c->S, A, c->st);
-  if (ngram_on(c))
+  prof_end(c, NC_K_VOCAB, A.B * V * 4.0 * (2 + 2 + 2 + 2 + 1), A.B * V * 12.0);
+  if (ngram_on(c)) {
+    prof_begin(c, NC_K_NGRAM);
     launch_ngram_predict(c->vp, c->S, A.rows, A.B, c->ngp.p, A.decode ? A.step_out : nullptr,
                          A.out, c->st);
+    prof_end(c, NC_K_NGRAM, A.B * V * 4.0 * 2, A.B * V * 8.0);
+  }
 }
 
 void check_config(const nc_config* cfg) {
@@ -680,6 +857,7 @@ nc_status nc_create(const nc_config* cfg, const float* w, nc_ctx** out) {
     c->g_final = static_cast<float*>(dmalloc(c.get(), d * 4));
     NC_HIP(hipMemcpy(c->g_final, p, d * 4, hipMemcpyHostToDevice));
     c->amax.alloc(4 * c->nl + 1);
+
     c->fp8_ready = c->prec != P_FP8;
     VocabParams& P = c->vp;
     P.V = c->V;
@@ -699,7 +877,7 @@ nc_status nc_create(const nc_config* cfg, const float* w, nc_ctx** out) {
     P.skip_mode = cfg->skip_mode;
     P.skip_bits = cfg->skip_entropy_bits;
     P.skip_pmax = cfg->skip_pmax;
-    NC_HIP(hipStreamSynchronize(c->st));
+    sync(c.get());
     *out = c.release();
   });
 }
@@ -734,7 +912,6 @@ nc_status nc_calibrate_fp8(nc_ctx* c, const int32_t* tokens, size_t n) {
     NC_HIP(hipMemsetAsync(v32.p, 0, kvb, c->st));
     std::swap(c->kc, k32);
     std::swap(c->vc, v32);
-    DevBuf<int32_t> ar;
     try {
       const int C = c->cfg.slide;
       for (size_t a = 0; a < n; a += C) {
@@ -743,15 +920,19 @@ nc_status nc_calibrate_fp8(nc_ctx* c, const int32_t* tokens, size_t n) {
           rows.push_back(RowMeta{0, int(j), j == 0 ? kBOS : tokens[j - 1], 0});
         BodyOpts o;
         o.calib = true;
-        run_body(c, rows, o);
-        std::vector<int32_t> idx(rows.size());
+        PassPlan p = plan_pass(c, std::move(rows), true);
+        std::vector<int32_t> idx(p.rows.size());
         std::iota(idx.begin(), idx.end(), 0);
-        ar.alloc(idx.size());
-        h2d(c, ar.p, idx.data(), idx.size());
+        Stage stg;
+        stage_pass(stg, p);
+        const size_t off_ar = stg.put(idx.data(), idx.size() * 4);
+        const uint8_t* d = upload_stage(c, stg);
+        run_pass(c, p, d, o);
         DevBuf<float> zt;
-        zt.alloc(rows.size() * (size_t)c->V);
-        run_lm_head(c, c->x.p, ar.p, int(rows.size()), zt.p, true);
-        NC_HIP(hipStreamSynchronize(c->st));
+        zt.alloc(p.rows.size() * (size_t)c->V);
+        run_lm_head(c, c->x.p, c->xinv.p, reinterpret_cast<const int32_t*>(d + off_ar), int(p.rows.size()),
+                    zt.p, true);
+        sync(c);
         zt.release();
       }
     } catch (...) {
@@ -759,7 +940,6 @@ nc_status nc_calibrate_fp8(nc_ctx* c, const int32_t* tokens, size_t n) {
       std::swap(c->vc, v32);
       k32.release();
       v32.release();
-      ar.release();
       c->att = att_save;
       throw;
     }
@@ -767,7 +947,6 @@ nc_status nc_calibrate_fp8(nc_ctx* c, const int32_t* tokens, size_t n) {
     std::swap(c->vc, v32);
     k32.release();
     v32.release();
-    ar.release();
     c->att = att_save;
     std::vector<float> am(c->amax.n);
     d2h(c, am.data(), c->amax.p, am.size());
@@ -804,16 +983,16 @@ nc_status nc_probs_for_context(nc_ctx* c, uint32_t s, const int32_t* tokens, siz
     for (size_t j = h.size(); j < n; ++j) {
       NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc + j, tokens + j, 4,
                             hipMemcpyHostToDevice, c->st));
-      catch_up(c, {int(s)}, {int(j)});
-      run_lm_head(c, c->hlast.p, c->steprows.p, 1, c->z.p);
+      catch_up_now(c, int(s), int(j));
+      run_lm_head(c, c->hlast.p, c->hinv.p, c->steprows.p, 1, c->z.p);
       StepArgs A = step_args(c, 1, false);
       A.step_out = nullptr;
       vocab_commit_step(c, A);
       h.push_back(tokens[j]);
     }
     // distribution of position n
-    catch_up(c, {int(s)}, {int(n)});
-    run_lm_head(c, c->hlast.p, c->steprows.p, 1, c->z.p);
+    catch_up_now(c, int(s), int(n));
+    run_lm_head(c, c->hlast.p, c->hinv.p, c->steprows.p, 1, c->z.p);
     c->dbgp.alloc(c->V);
     c->dbgpt.alloc(c->V);
     c->dbgcdf.alloc(c->V + 1);
@@ -826,7 +1005,7 @@ nc_status nc_probs_for_context(nc_ctx* c, uint32_t s, const int32_t* tokens, siz
     A.dbg_pt = c->dbgpt.p;
     A.dbg_cdf = c->dbgcdf.p;
     launch_vocab_step(c->vp, c->S, A, c->st);  // probe: no state update is launched
-    NC_HIP(hipStreamSynchronize(c->st));
+    sync(c);
     d2h(c, probs, c->dbgp.p, c->V);
     if (probe) {
       int32_t mode = 0;
@@ -862,12 +1041,12 @@ nc_status nc_mix_update(nc_ctx* c, uint32_t s, int32_t token) {
     h2d(c, c->steprows.p, &sid, 1);
     NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc + j, &token, 4,
                           hipMemcpyHostToDevice, c->st));
-    catch_up(c, {int(s)}, {int(j)});
-    run_lm_head(c, c->hlast.p, c->steprows.p, 1, c->z.p);
+    catch_up_now(c, int(s), int(j));
+    run_lm_head(c, c->hlast.p, c->hinv.p, c->steprows.p, 1, c->z.p);
     StepArgs A = step_args(c, 1, false);
     A.step_out = nullptr;
     vocab_commit_step(c, A);
-    NC_HIP(hipStreamSynchronize(c->st));
+    sync(c);
     h.push_back(token);
   });
 }
@@ -906,12 +1085,11 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
       NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc, tokens[s], n_tokens[s] * 4,
                             hipMemcpyHostToDevice, c->st));
     }
-    NC_HIP(hipStreamSynchronize(c->st));
+    sync(c);
     h2d(c, c->steprows.p, order.data(), order.size());
     if (ngram_on(c))
       launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
     const int C = c->cfg.slide;
-    DevBuf<int32_t> seg_arows;
     for (size_t a = 0; a < maxn; a += C) {
       // prefill: x positions [a, a + C) of every stream still active (teacher forcing)
       std::vector<RowMeta> rows;
@@ -923,7 +1101,7 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
         for (size_t j = a; j < std::min(n_tokens[s], a + C); ++j)
           rows.push_back(RowMeta{s, int(j), j == 0 ? kBOS : tokens[s][j - 1], 0});
       }
-      run_body(c, rows);
+      PassPlan plan = plan_pass(c, std::move(rows));
       const size_t seg_len = std::min((size_t)C, maxn - a);
       std::vector<int32_t> ar(seg_len * n, 0);
       std::vector<int> active(seg_len, 0);
@@ -933,11 +1111,15 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
             ar[i * n + k] = off[k] + int(i);
             active[i] = k + 1;
           }
-      seg_arows.alloc(ar.size());
-      h2d(c, seg_arows.p, ar.data(), ar.size());
+      Stage stg;
+      stage_pass(stg, plan);
+      const size_t off_ar = stg.put(ar.data(), ar.size() * 4);
+      const uint8_t* dst = upload_stage(c, stg);
+      run_pass(c, plan, dst);
+      const int32_t* seg_ar = reinterpret_cast<const int32_t*>(dst + off_ar);
       for (size_t i = 0; i < seg_len; ++i) {
         const int B = active[i];
-        run_lm_head(c, c->x.p, seg_arows.p + i * n, B, c->z.p);
+        run_lm_head(c, c->x.p, c->xinv.p, seg_ar + i * n, B, c->z.p);
         StepArgs A = step_args(c, B, false);
         A.step_out = nullptr;
         A.iv = c->iv.p;
@@ -945,7 +1127,7 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
         vocab_commit_step(c, A);
       }
     }
-    NC_HIP(hipStreamSynchronize(c->st));
+    sync(c);
     // host coder, one thread per stream
     std::vector<std::vector<uint32_t>> ivs(n);
     std::vector<std::vector<float>> pts(n);
@@ -1032,15 +1214,21 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
           llm.push_back(order[k]);
           upto.push_back(int(i));
         }
+      std::vector<PassPlan> plans;
+      if (!llm.empty()) plans = plan_catch_up(c, llm, upto);
+      for (int k = 0; k < B; ++k) tg[k] = dec[order[k]].target();
+      Stage stg;
+      for (auto& p : plans) stage_pass(stg, p);
+      const size_t off_tg = stg.put(tg.data(), size_t(B) * 4);
+      const uint8_t* dst = upload_stage(c, stg);
+      for (auto& p : plans) run_pass(c, p, dst);
       if (!llm.empty()) {
-        catch_up(c, llm, upto);
-        run_lm_head(c, c->hlast.p, c->steprows.p, B, c->z.p);
+        run_lm_head(c, c->hlast.p, c->hinv.p, c->steprows.p, B, c->z.p);
         c->stats.llm_rows += llm.size();
       }
       c->stats.skipped += B - llm.size();
-      for (int k = 0; k < B; ++k) tg[k] = dec[order[k]].target();
-      h2d(c, c->targets.p, tg.data(), B);
       StepArgs A = step_args(c, B, true);
+      A.targets = reinterpret_cast<const uint32_t*>(dst + off_tg);
       vocab_commit_step(c, A);
       if (!ngram_on(c)) {
         // no n-gram stage: pack the outcome here (mode stays LLM)
@@ -1064,6 +1252,26 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
     for (int s = 0; s < n; ++s) c->stats.tokens += n_tokens[s];
     c->stats.seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+}
+
+nc_status nc_profile(nc_ctx* c, int32_t cls) {
+  return guard([&] {
+    NC_CHECK(c, NC_E_INVALID, "NULL context");
+    NC_CHECK(cls >= -1 && cls < NC_K_COUNT, NC_E_INVALID, "bad kernel class");
+    NC_HIP(hipSetDevice(c->dev));
+    sync(c);
+    c->prof_class = cls;
+    c->prof = nc_kstat{};
+  });
+}
+
+nc_status nc_profile_read(nc_ctx* c, nc_kstat* out) {
+  return guard([&] {
+    NC_CHECK(c && out, NC_E_INVALID, "NULL argument");
+    NC_HIP(hipSetDevice(c->dev));
+    sync(c);
+    *out = c->prof;
   });
 }
 
