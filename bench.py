@@ -13,9 +13,11 @@ same workload on the host cores.
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,6 +34,13 @@ KERNEL_SOURCES = {"qkv": "k_llm.hip", "attn": "k_llm.hip", "oproj": "k_llm.hip",
                   "vocab": "k_vocab.hip", "ngram": "k_vocab.hip"}
 
 
+# rocprofv3 kernel names of each class (demangled); oproj and down share one kernel and have none
+KERNEL_NAME_RE = {"qkv": r"gemm_\w*kernel<\d+, \d+, 3\b", "gateup": r"gemm_\w*kernel<\d+, \d+, 2\b",
+                  "lmhead": r"gemm_\w*kernel<\d+, \d+, 0\b", "attn": r"attention_\w*kernel",
+                  "vocab": r"(vocab_\w*|ensemble_bias)_kernel", "ngram": r"ngram_\w*_kernel"}
+PROBE_RE = r"neg"   # the plain streaming probe kernel (torch.neg: reads N bytes, writes N bytes)
+
+
 def kernel_source_hash(kernel: str) -> str:
     p = os.path.join(ROOT, "paper_2602_19626_amd", "csrc", KERNEL_SOURCES[kernel])
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
@@ -46,6 +55,40 @@ def load_traffic(kernel: str, workload: str):
     if t.get("source_sha") != kernel_source_hash(kernel):
         return None
     return t.get("bytes_per_launch")
+
+
+def traffic_from(fetch_csv: str, write_csv: str, kernel: str, workload: str, probe_mib: int,
+                 command: str) -> dict:
+    """HBM bytes per launch of a kernel class from two rocprofv3 --pmc counter files (FETCH_SIZE,
+    WRITE_SIZE, KiB per dispatch), each scaled by the same counter's reading for the streaming
+    probe of known size; written to profiles/traffic_<kernel>_<workload>.json."""
+    def per_kernel(path, counter):
+        out = {}
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] == counter:
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]) * 1024.0)
+        return out
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+    probe_bytes = probe_mib * (1 << 20)
+
+    def pick(d, pat):
+        return [v for name, vals in d.items() if re.search(pat, name) for v in vals]
+    pf, pw = pick(f, PROBE_RE), pick(w, PROBE_RE)
+    assert len(pf) == 1 and len(pw) == 1, "expected exactly one probe dispatch per counter run"
+    fscale, wscale = probe_bytes / pf[0], probe_bytes / pw[0]
+    kf, kw = pick(f, KERNEL_NAME_RE[kernel]), pick(w, KERNEL_NAME_RE[kernel])
+    assert kf and kw, f"no {kernel} dispatches in the counter files"
+    fb = sum(kf) / len(kf) * fscale
+    wb = sum(kw) / len(kw) * wscale
+    t = {"kernel": kernel, "workload": workload, "source_sha": kernel_source_hash(kernel),
+         "launches": len(kf), "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+         "bytes_per_launch": round(fb + wb), "probe_bytes": probe_bytes,
+         "fetch_scale": round(fscale, 5), "write_scale": round(wscale, 5), "command": command}
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    json.dump(t, open(path, "w"), indent=1)
+    return t
 
 
 def cpu_baseline(wl, weights, stream, n_sample: int):
@@ -78,7 +121,16 @@ def main():
     ap.add_argument("--n-streams", type=int, default=None)
     ap.add_argument("--cpu-sample", type=int, default=250)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain streaming kernel of this size first (counter scaling)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="offline: turn two rocprofv3 --pmc counter files into the traffic figure")
+    ap.add_argument("--traffic-command", default="", help="the counter runs' command, recorded")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_from(*args.traffic_from, args.kernel, args.workload,
+                                      args.copy_probe_mib, args.traffic_command)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (streams are "
               "independent and would be sharded by stream, one process per GPU)",
@@ -91,6 +143,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     wl = synth.WORKLOADS[args.workload]
     streams = synth.workload_streams(wl, max_len=args.max_len, n_streams=args.n_streams)
     n_tok = int(sum(len(s) for s in streams))
