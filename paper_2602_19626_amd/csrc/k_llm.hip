@@ -6,8 +6,8 @@
 // Batch invariance.  Every output element of a GEMM is the sum over K in chunks of 32 taken in
 // increasing order, each chunk by the same MFMA instruction (f32 16x16x4, bf16 16x16x32, fp8
 // 16x16x32), whatever the tile shape or the number of rows M.  Attention splits the keys into
-// 256-key chunks at fixed absolute positions and combines the chunk partials with one fixed
-// formula.  A token's logits are therefore bitwise the same whether it is evaluated in a
+// 64-key chunks at fixed absolute positions and combines the chunk partials with one fixed
+// two-level fold.  A token's logits are therefore bitwise the same whether it is evaluated in a
 // 32,768-row prefill or in a one-row decode step, which the coder relies on.
 #include "cdf_dev.hpp"
 #include "common.hpp"
@@ -109,8 +109,8 @@ __device__ __forceinline__ void atomic_max_abs(float* p, float v) {
 //     f32 16x16x4:            16 steps, step t / lane group g consumes k = 16 g + t,
 //     bf16 / fp8 16x16x32:     2 steps, step t / lane group g consumes k = 32 t + 8 g .. + 7,
 //   with entries beyond K read as zero.
-// The tile kernel (many rows) sums the parts as it walks K; the split kernel (few rows) computes
-// each part in its own wave and a reduce kernel adds the parts in order.  Both then apply the same
+// The tile kernels (many rows) sum the parts as they walk K; the split kernel (few rows) computes
+// each part in its own wave and the workgroup adds the parts in order.  Both then apply the same
 // epilogue function, so a row's outputs do not depend on how many rows are in the launch.
 
 constexpr int KP = 64;
@@ -475,16 +475,242 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
   }
 }
 
-// ---- split kernel (few rows): one workgroup per epilogue group ----
+// ---- wide tile kernel (prefill): 128x128 tiles, four 64x64 waves, double-buffered LDS ----
+//
+// For bf16 / fp8 with many rows.  Each K part is staged global -> registers -> LDS one part ahead
+// of the MFMAs, so one barrier per part suffices.  Tiles are ordered so that the workgroups of
+// one XCD (dispatch is round-robin over the 8 XCDs) take consecutive tiles of the same A rows,
+// which then stay in that XCD's L2 while every column tile reads them.  The QKV epilogue needs
+// both RoPE halves of a head in one wave: a wave's 64 columns are 64-aligned, so for hd = 64 the
+// partner of block j is block j ^ 2 and for hd = 32 block j ^ 1, in the same lane.
+
+constexpr int WBM = 128, WBN = 128, WTHREADS = 256;
+
+template <int P, int AM, int EPI>
+__global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a, int tiles_m,
+                                                             int tiles_n) {
+  constexpr int ES = PT<P>::ES;
+  constexpr int ROWB = KP * ES + 16;
+  constexpr int TILEB = (WBM + WBN) * ROWB;
+  constexpr int CPR = KP * ES / 16;                     // 16-byte chunks per staged row
+  constexpr int NB16 = WBN * CPR / WTHREADS;            // W chunks per thread
+  constexpr int NA16 = WBM * CPR / WTHREADS;            // A chunks per thread (A_DIRECT)
+  constexpr int NAF = WBM * (KP / 4) / WTHREADS;        // float4 A chunks per thread (A_NORM)
+  __shared__ __align__(16) uint8_t lds[2 * TILEB];
+  __shared__ float s_inv[WBM];
+  __shared__ int s_arow[WBM];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int K = a.K, S = (K + KP - 1) / KP;
+
+  // XCD-aware tile order (a bijection of [0, tiles)): XCD x owns a contiguous range of tiles
+  const int nt = tiles_m * tiles_n, q = nt / 8, r8 = nt % 8;
+  const int bx = blockIdx.x, xcd = bx % 8, slot = bx / 8;
+  const int t = xcd * q + min(xcd, r8) + slot;
+  const int m0 = (t / tiles_n) * WBM, n0 = (t % tiles_n) * WBN;
+
+  for (int r = tid; r < WBM; r += WTHREADS) {
+    const int m = m0 + r;
+    s_arow[r] = m < a.M ? (a.a_rows ? a.a_rows[m] : m) : -1;
+  }
+  __syncthreads();
+  if constexpr (AM == A_NORM) {
+    const float* X = static_cast<const float*>(a.A);
+    for (int r = wave; r < WBM; r += WTHREADS / 64) {
+      const int ar = s_arow[r];
+      float v = 0.f;
+      if (ar >= 0) v = a.inv ? a.inv[ar] : row_inv_rms(X + (long long)ar * K, K, a.eps, lane);
+      if (lane == 0) s_inv[r] = v;
+    }
+    __syncthreads();
+  }
+
+  // global -> register staging of one K part
+  v4f xa[AM == A_NORM ? NAF : 1];
+  v4f ga;
+  v4i ra[AM == A_NORM ? 1 : NA16];
+  v4i rb[NB16];
+  const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
+  auto fetch = [&](int k0) {
+    if constexpr (AM == A_NORM) {
+      const float* X = static_cast<const float*>(a.A);
+      const int kc = tid % (KP / 4), k = k0 + kc * 4;  // fixed per thread
+      ga = k < K ? *reinterpret_cast<const v4f*>(a.gain + k) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int u = 0; u < NAF; ++u) {
+        const int r = tid / (KP / 4) + u * (WTHREADS / (KP / 4));
+        const int ar = s_arow[r];
+        xa[u] = (ar >= 0 && k < K) ? *reinterpret_cast<const v4f*>(X + (long long)ar * K + k)
+                                   : v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    } else {
+      const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
+#pragma unroll
+      for (int u = 0; u < NA16; ++u) {
+        const int c = tid + u * WTHREADS, r = c / CPR, k = k0 + (c % CPR) * (16 / ES);
+        const int ar = s_arow[r];
+        ra[u] = (ar >= 0 && k < K) ? *reinterpret_cast<const v4i*>(A8 + ((long long)ar * K + k) * ES)
+                                   : v4i{0, 0, 0, 0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NB16; ++u) {
+      const int c = tid + u * WTHREADS, r = c / CPR, k = k0 + (c % CPR) * (16 / ES);
+      const int n = n0 + r;
+      rb[u] = (n < a.N && k < K) ? *reinterpret_cast<const v4i*>(W8 + ((long long)n * K + k) * ES)
+                                 : v4i{0, 0, 0, 0};
+    }
+  };
+  float amax = 0.f;
+  const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
+  auto stage = [&](uint8_t* buf) {
+    uint8_t* la = buf;
+    uint8_t* lb = buf + WBM * ROWB;
+    if constexpr (AM == A_NORM) {
+      const int kc = tid % (KP / 4);
+#pragma unroll
+      for (int u = 0; u < NAF; ++u) {
+        const int r = tid / (KP / 4) + u * (WTHREADS / (KP / 4));
+        const float iv = s_inv[r];
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          v[i] = xa[u][i] * iv * ga[i];  // the same expression as norm4
+          amax = fmaxf(amax, fabsf(v[i]));
+        }
+        PT<P>::put4(la + r * ROWB + kc * 4 * ES, v, a_inv);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NA16; ++u) {
+        const int c = tid + u * WTHREADS;
+        *reinterpret_cast<v4i*>(la + (c / CPR) * ROWB + (c % CPR) * 16) = ra[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NB16; ++u) {
+      const int c = tid + u * WTHREADS;
+      *reinterpret_cast<v4i*>(lb + (c / CPR) * ROWB + (c % CPR) * 16) = rb[u];
+    }
+  };
+
+  v4f tot[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tot[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  fetch(0);
+  stage(lds);
+  __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    if (s + 1 < S) fetch((s + 1) * KP);
+    const uint8_t* la = lds + (s & 1) * TILEB;
+    const uint8_t* lb = la + WBM * ROWB;
+    typename Frag<P>::T bf[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Frag<P>::load(bf[j], lb + (wn * 64 + j * 16 + fr) * ROWB, fg);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      typename Frag<P>::T af;
+      Frag<P>::load(af, la + (wm * 64 + i * 16 + fr) * ROWB, fg);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        Frag<P>::mma(acc, af, bf[j]);
+        tot[i][j] += acc;
+      }
+    }
+    if (s + 1 < S) stage(lds + ((s + 1) & 1) * TILEB);
+    __syncthreads();
+  }
+  if (a.a_amax) {
+    amax = wave_max_f(amax);
+    if (lane == 0) atomic_max_abs(a.a_amax, amax);
+  }
+
+  const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
+  const int mw = m0 + wm * 64, nw = n0 + wn * 64;
+  if constexpr (EPI == E_STORE || EPI == E_RESID) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = mw + i * 16 + fg * 4 + e;
+        if (m >= a.M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = nw + j * 16 + fr;
+          if (n >= a.N) continue;
+          float* o = a.out_f32 + (long long)m * a.ldo + n;
+          if constexpr (EPI == E_RESID)
+            *o += tot[i][j][e] * deq;
+          else
+            *o = tot[i][j][e] * deq;
+        }
+      }
+  } else if constexpr (EPI == E_GLU) {
+    float omax = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = mw + i * 16 + fg * 4 + e;
+        if (m >= a.M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; j += 2) {
+          const int col = ((nw + j * 16) / 32) * 16 + fr;
+          if (col < a.N / 2)
+            omax = fmaxf(omax, emit_glu<P>(a, m, col, tot[i][j][e] * deq, tot[i][j + 1][e] * deq));
+        }
+      }
+    if (a.out_amax) {
+      omax = wave_max_f(omax);
+      if (lane == 0) atomic_max_abs(a.out_amax, omax);
+    }
+  } else if constexpr (EPI == E_QKV) {
+    const int nqk = (a.Hq + a.Hk) * a.hd;
+    const int px = a.hd == 64 ? 2 : 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = mw + i * 16 + fg * 4 + e;
+        if (m >= a.M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = nw + j * 16 + fr;
+          if (n >= a.N) continue;
+          const float partner = n < nqk ? tot[i][j ^ px][e] * deq : 0.f;
+          emit_qkv_prec(a, P_BF16, m, n, tot[i][j][e] * deq, partner);
+        }
+      }
+  }
+}
+
+template <int P, int AM, int EPI>
+static void gemm_wide(const GemmArgs& a, hipStream_t s) {
+  const int tm = (a.M + WBM - 1) / WBM, tn = (a.N + WBN - 1) / WBN;
+  hipLaunchKernelGGL((gemm_wide_kernel<P, AM, EPI>), dim3(tm * tn), dim3(WTHREADS), 0, s, a, tm,
+                     tn);
+}
+
+// ---- split kernel (fewer than 256 rows): one workgroup per (epilogue group, 64-row chunk) ----
 //
 // A group is the set of 16-column blocks one epilogue needs together: a RoPE pair of blocks
-// {b, b + hd/32} for QKV (a single block when hd = 16), a gate/up block pair for the SiLU-gated MLP,
-// one block otherwise.  The group's (block, K-part) items are spread over up to 16 waves; each
-// item's partial (its part's MFMA chain from zero) goes to LDS, and after one barrier the
-// workgroup adds each output's parts in order and applies the epilogue.  No cross-workgroup
-// communication is needed.
+// {b, b + hd/32} for QKV (a single block when hd = 16), a gate/up block pair for the SiLU-gated
+// MLP, two adjacent blocks for plain stores, one block for residual adds.  Wave w takes K parts
+// w, w + nw, ...: for a part it issues the loads of the chunk's A fragments and the group's W
+// fragments together, runs every (row block, column block) MFMA chain from zero and leaves the
+// partial in LDS.  After one barrier the workgroup adds each output's partials in part order and
+// applies the epilogue.  A arrives normalised and quantised (norm_quant_kernel), so nothing but
+// loads precedes the MFMAs.  No cross-workgroup communication is needed.
 
 constexpr int SPLIT_WAVES = 16;
+constexpr int SPLIT_ROWS = 64;
+constexpr int SKINNY_ROWS = 256;  // below this many rows the split kernel is used
 
 __global__ void row_rms_kernel(const GemmArgs a, float* __restrict__ inv) {
   const int m = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
@@ -496,7 +722,39 @@ __global__ void row_rms_kernel(const GemmArgs a, float* __restrict__ inv) {
   if (lane == 0) inv[ar] = v;
 }
 
-// Blocks of group gi: QKV pairs blocks (b, b + half) within a head, GLU pairs (2j, 2j + 1).
+// y[m] = quantise(x[a_rows[m]] * inv * gain): the A operand of a normed GEMM, element for element
+// the value the fused prologues of the tile kernels produce.  One wave per row.
+template <int P>
+__global__ __launch_bounds__(256) void norm_quant_kernel(const GemmArgs a, void* __restrict__ y) {
+  constexpr int ES = PT<P>::ES;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= a.M) return;
+  const int K = a.K;
+  const int ar = a.a_rows ? a.a_rows[m] : m;
+  const float* xrow = static_cast<const float*>(a.A) + (long long)ar * K;
+  const float iv = a.inv ? a.inv[ar] : row_inv_rms(xrow, K, a.eps, lane);
+  const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
+  uint8_t* yrow = static_cast<uint8_t*>(y) + (long long)m * K * ES;
+  float amax = 0.f;
+  for (int k = lane * 4; k < K; k += 256) {
+    float v[4];
+    norm4(xrow, a.gain, k, K, iv, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(v[i]));
+    PT<P>::put4(yrow + (long long)k * ES, v, a_inv);
+  }
+  if (a.a_amax) {
+    amax = wave_max_f(amax);
+    if (lane == 0) atomic_max_abs(a.a_amax, amax);
+  }
+}
+
+__host__ __device__ __forceinline__ int group_size(int epi, int hd) {
+  if (epi == E_QKV) return hd == 16 ? 1 : 2;
+  return epi == E_RESID ? 1 : 2;
+}
+
+// Block j of group gi: QKV pairs blocks (b, b + half) within a head, the others take 2 gi + j.
 __device__ __forceinline__ int group_block(int epi, int hd, int gi, int j) {
   if (epi == E_QKV) {
     const int nb = hd / 16;  // blocks per head
@@ -505,97 +763,70 @@ __device__ __forceinline__ int group_block(int epi, int hd, int gi, int j) {
     const int head = gi / half, r = gi % half;
     return head * nb + r + j * half;
   }
-  if (epi == E_GLU) return 2 * gi + j;
-  return gi;
+  if (epi == E_RESID) return gi;
+  return 2 * gi + j;
 }
 
-template <int P, int AM, int EPI, int MB>
+template <int P, int EPI, int MB>
 __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const GemmArgs a) {
   constexpr int ES = PT<P>::ES;
-  constexpr int G = (EPI == E_GLU || EPI == E_QKV) ? 2 : 1;
-  extern __shared__ float lds[];  // [items][MB*16 rows][16 cols] partials, then inv[MB*16]
+  extern __shared__ float lds[];  // partials [part][block j][row block][16 rows][16 cols]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
-  const int K = a.K, M = a.M, N = a.N;
+  const int K = a.K, N = a.N;
   const int S = (K + KP - 1) / KP;
-  const int gi = blockIdx.x;
-  const int gsize = (EPI == E_QKV && a.hd == 16) ? 1 : G;
-  const int items = gsize * S;
-  float* part = lds;
-  float* s_inv = lds + items * MB * 256;
-  const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
-  float amax = 0.f;
-  // weight fragment of item it (W is read once; its loads are issued ahead of their use)
-  auto load_w = [&](int it, typename Frag<P>::T& bf) {
-    const int n = group_block(EPI, a.hd, gi, it / S) * 16 + fr;
-    if (n < N)
-      Frag<P>::load_raw(bf, static_cast<const uint8_t*>(a.W) + (long long)n * K * ES,
-                        (it % S) * KP, K, fg);
-    else
-      Frag<P>::zero(bf);
-  };
-  typename Frag<P>::T bnext;
-  if (wave < items) load_w(wave, bnext);
-  if constexpr (AM == A_NORM) {
-    for (int m = wave; m < M; m += nw) {
-      const int ar = a.a_rows ? a.a_rows[m] : m;
-      const float v = a.inv ? a.inv[ar]
-                            : row_inv_rms(static_cast<const float*>(a.A) + (long long)ar * K, K,
-                                          a.eps, lane);
-      if (lane == 0) s_inv[m] = v;
+  const int gi = blockIdx.x, r0 = blockIdx.y * SPLIT_ROWS;
+  const int M = min(a.M - r0, SPLIT_ROWS);
+  const int gs = group_size(EPI, a.hd);
+  const uint8_t* A8 = static_cast<const uint8_t*>(a.A) + (long long)r0 * K * ES;
+  const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
+  for (int s = wave; s < S; s += nw) {
+    const int k0 = s * KP;
+    typename Frag<P>::T bf[2], af[MB];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = group_block(EPI, a.hd, gi, j) * 16 + fr;
+      if (j < gs && n < N)
+        Frag<P>::load_raw(bf[j], W8 + (long long)n * K * ES, k0, K, fg);
+      else
+        Frag<P>::zero(bf[j]);
     }
-    __syncthreads();
-  }
-  for (int it = wave; it < items; it += nw) {
-    const int k0 = (it % S) * KP;
-    typename Frag<P>::T bf;
-    __builtin_memcpy(&bf, &bnext, sizeof(bf));
-    if (it + nw < items) load_w(it + nw, bnext);
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
-      const int mrow = rb * 16 + fr;
-      typename Frag<P>::T af;
-      if (mrow < M) {
-        const int ar = a.a_rows ? a.a_rows[mrow] : mrow;
-        if constexpr (AM == A_NORM) {
-          const float* xrow = static_cast<const float*>(a.A) + (long long)ar * K;
-          const float iv = s_inv[mrow];
-          auto nf = [&](int k, float (&v)[4]) { norm4(xrow, a.gain, k, K, iv, v); };
-          Frag<P>::load_norm(af, nf, k0, fg, a_inv, amax);
-        } else {
-          Frag<P>::load_raw(af, static_cast<const uint8_t*>(a.A) + (long long)ar * K * ES, k0, K,
-                            fg);
-        }
-      } else {
-        Frag<P>::zero(af);
-      }
-      v4f acc = {0.f, 0.f, 0.f, 0.f};
-      Frag<P>::mma(acc, af, bf);
+      const int m = rb * 16 + fr;
+      if (m < M)
+        Frag<P>::load_raw(af[rb], A8 + (long long)m * K * ES, k0, K, fg);
+      else
+        Frag<P>::zero(af[rb]);
+    }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) part[(it * MB + rb) * 256 + (fg * 4 + e) * 16 + fr] = acc[e];
+    for (int j = 0; j < 2; ++j) {
+      if (j >= gs) break;
+#pragma unroll
+      for (int rb = 0; rb < MB; ++rb) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        Frag<P>::mma(acc, af[rb], bf[j]);
+        float* dst = lds + (((s * gs + j) * MB + rb) << 8);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[(fg * 4 + e) * 16 + fr] = acc[e];
+      }
     }
   }
   __syncthreads();
-  if (a.a_amax) {
-    amax = wave_max_f(amax);
-    if (lane == 0) atomic_max_abs(a.a_amax, amax);
-  }
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
-  // output (m, block j, column c) = sum over parts s in order
+  // output (row m of the chunk, block j, column c) = partials summed in part order
   auto sum = [&](int m, int j, int c) {
     float v = 0.f;
-    for (int s = 0; s < S; ++s) {
-      const int it = j * S + s;
-      v += part[(it * MB + m / 16) * 256 + (m % 16) * 16 + c];
-    }
+    for (int s = 0; s < S; ++s) v += lds[(((s * gs + j) * MB + (m >> 4)) << 8) + (m & 15) * 16 + c];
     return v * deq;
   };
   if constexpr (EPI == E_GLU) {
     float omax = 0.f;
     for (int t = threadIdx.x; t < M * 16; t += blockDim.x) {
-      const int m = t / 16, c = t % 16;
+      const int m = t >> 4, c = t & 15;
       const int col = gi * 16 + c;
-      if (col < N / 2) omax = fmaxf(omax, emit_glu<P>(a, m, col, sum(m, 0, c), sum(m, 1, c)));
+      if (col < N / 2)
+        omax = fmaxf(omax, emit_glu<P>(a, r0 + m, col, sum(m, 0, c), sum(m, 1, c)));
     }
     if (a.out_amax) {
       omax = wave_max_f(omax);
@@ -603,25 +834,20 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
     }
   } else {
     const int nqk = (a.Hq + a.Hk) * a.hd;
-    for (int t = threadIdx.x; t < M * gsize * 16; t += blockDim.x) {
-      const int m = t / (gsize * 16), j = (t / 16) % gsize, c = t % 16;
+    for (int t = threadIdx.x; t < M * gs * 16; t += blockDim.x) {
+      const int m = t / (gs * 16), j = (t >> 4) % gs, c = t & 15;
       const int n = group_block(EPI, a.hd, gi, j) * 16 + c;
       if (n >= N) continue;
       const float v = sum(m, j, c);
+      const long long row = r0 + m;
       if constexpr (EPI == E_STORE) {
-        a.out_f32[(long long)m * a.ldo + n] = v;
+        a.out_f32[row * a.ldo + n] = v;
       } else if constexpr (EPI == E_RESID) {
-        a.out_f32[(long long)m * a.ldo + n] += v;
+        a.out_f32[row * a.ldo + n] += v;
       } else {
         float partner = 0.f;
-        if (n < nqk) {
-          if (a.hd == 16) {
-            partner = sum(m, 0, c < 8 ? c + 8 : c - 8);
-          } else {
-            partner = sum(m, 1 - j, c);
-          }
-        }
-        emit_qkv_prec(a, P == P_F32 ? P_F32 : P_BF16, m, n, v, partner);
+        if (n < nqk) partner = a.hd == 16 ? sum(m, 0, c ^ 8) : sum(m, 1 - j, c);
+        emit_qkv_prec(a, P == P_F32 ? P_F32 : P_BF16, int(row), n, v, partner);
       }
     }
   }
@@ -1036,50 +1262,41 @@ static void gemm_go(const GemmArgs& a, hipStream_t s) {
 
 constexpr size_t kSplitLdsMax = 144 * 1024;  // of the 160 KiB LDS of a gfx950 CU
 
-template <int P, int AM, int EPI, int MB>
+template <int P, int EPI, int MB>
 static void launch_split(dim3 grid, dim3 block, size_t lds, const GemmArgs& a, hipStream_t s) {
   static bool raised = false;  // allow more than the default 64 KiB of dynamic LDS, once
   if (!raised) {
-    NC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_split_kernel<P, AM, EPI, MB>),
+    NC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_split_kernel<P, EPI, MB>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(kSplitLdsMax)));
     raised = true;
   }
-  hipLaunchKernelGGL((gemm_split_kernel<P, AM, EPI, MB>), grid, block, lds, s, a);
+  hipLaunchKernelGGL((gemm_split_kernel<P, EPI, MB>), grid, block, lds, s, a);
 }
 
-template <int P, int AM, int EPI>
+static int split_mb(int M) { return std::min((M + 15) / 16, SPLIT_ROWS / 16); }
+
+static size_t split_lds(const GemmArgs& a, int epi) {
+  const int S = (a.K + KP - 1) / KP;
+  return size_t(S) * group_size(epi, a.hd) * split_mb(a.M) * 256 * sizeof(float);
+}
+
+// a.A is the quantised A operand ([M][K], precision P), a.a_rows unused
+template <int P, int EPI>
 static void gemm_split(const GemmArgs& a, hipStream_t s) {
   const int S = (a.K + KP - 1) / KP;
   const int nblk = (a.N + 15) / 16;
-  int ngroups, gsize;
-  if (EPI == E_GLU) {
-    gsize = 2;
-    ngroups = nblk / 2;
-  } else if (EPI == E_QKV && a.hd > 16) {
-    gsize = 2;
-    ngroups = nblk / 2;
-  } else {
-    gsize = 1;
-    ngroups = nblk;
-  }
-  const int mb = (a.M + 15) / 16;
-  const int items = gsize * S;
-  const int waves = items < SPLIT_WAVES ? items : SPLIT_WAVES;
-  const size_t lds = (size_t(items) * mb * 256 + mb * 16) * sizeof(float);
-  const dim3 grid(ngroups), block(64 * waves);
+  const int gs = group_size(EPI, a.hd);
+  const int ngroups = (nblk + gs - 1) / gs;
+  const int mb = split_mb(a.M);
+  const int waves = S < SPLIT_WAVES ? S : SPLIT_WAVES;
+  const dim3 grid(ngroups, (a.M + SPLIT_ROWS - 1) / SPLIT_ROWS), block(64 * waves);
+  const size_t lds = split_lds(a, EPI);
   switch (mb) {
-    case 1: launch_split<P, AM, EPI, 1>(grid, block, lds, a, s); break;
-    case 2: launch_split<P, AM, EPI, 2>(grid, block, lds, a, s); break;
-    case 3: launch_split<P, AM, EPI, 3>(grid, block, lds, a, s); break;
-    default: launch_split<P, AM, EPI, 4>(grid, block, lds, a, s); break;
+    case 1: launch_split<P, EPI, 1>(grid, block, lds, a, s); break;
+    case 2: launch_split<P, EPI, 2>(grid, block, lds, a, s); break;
+    case 3: launch_split<P, EPI, 3>(grid, block, lds, a, s); break;
+    default: launch_split<P, EPI, 4>(grid, block, lds, a, s); break;
   }
-}
-
-static bool split_fits(const GemmArgs& a, int epi) {
-  const int S = (a.K + KP - 1) / KP;
-  const int gsize = (epi == E_GLU || (epi == E_QKV && a.hd > 16)) ? 2 : 1;
-  const int mb = (a.M + 15) / 16;
-  return (size_t(gsize) * S * mb * 256 + mb * 16) * sizeof(float) <= kSplitLdsMax;
 }
 
 void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s) {
@@ -1088,12 +1305,27 @@ void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s) {
   NC_HIP(hipGetLastError());
 }
 
+size_t gemm_workspace_bytes(int rows, int K) { return size_t(rows) * K * sizeof(float); }
+
 template <int P, int AM, int EPI>
 static void gemm_shape(const GemmArgs& a, hipStream_t s) {
-  // few rows: spread K over waves; lm_head-sized N with more rows: the tile kernel has enough
-  // workgroups by itself
-  if (a.M <= 64 && split_fits(a, EPI) && (a.M <= 16 || (long long)a.N * a.K <= (4ll << 20)))
-    return gemm_split<P, AM, EPI>(a, s);
+  if (a.M < SKINNY_ROWS && split_lds(a, EPI) <= kSplitLdsMax) {
+    GemmArgs b = a;
+    if constexpr (AM == A_NORM) {
+      NC_CHECK(a.a_ws && a.a_ws_bytes >= size_t(a.M) * a.K * PT<P>::ES, NC_E_INVALID,
+               "GEMM workspace too small");
+      hipLaunchKernelGGL(norm_quant_kernel<P>, dim3((a.M + 3) / 4), dim3(256), 0, s, a, a.a_ws);
+      b.A = a.a_ws;
+    } else {
+      NC_CHECK(a.a_rows == nullptr, NC_E_INVALID, "row gather needs a normed GEMM");
+    }
+    b.a_rows = nullptr;
+    return gemm_split<P, EPI>(b, s);
+  }
+  if constexpr (P != P_F32) {
+    if (a.M >= SKINNY_ROWS && (EPI != E_QKV || a.hd == 32 || a.hd == 64))
+      return gemm_wide<P, AM, EPI>(a, s);
+  }
   if constexpr (EPI == E_GLU) {
     if (a.M <= 64)
       gemm_go<P, AM, EPI, 16, 32, 1, 2>(a, s);

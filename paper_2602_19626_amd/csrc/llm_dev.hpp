@@ -42,8 +42,9 @@ struct GemmArgs {
   void* vt_cache;         // [stream][kvh][hd][R]
   long long kv_stride;    // elements per stream in k_cache / vt_cache (one layer)
   int Hq, Hk, hd, ring;
-  // split path (rows <= 64)
   const float* inv;       // A_NORM: precomputed inverse RMS per A row (indexed like A), or null
+  void* a_ws;             // A_NORM with few rows: the quantised A operand is staged here
+  size_t a_ws_bytes;      // at least gemm_workspace_bytes(M, K)
 };
 
 // Attention work item: a block of up to 16 (query, head) columns of one stream and kv head.
@@ -78,6 +79,7 @@ struct AttnArgs {
 void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s);
 // inverse RMS (row_inv_rms) of rows a.A[a_rows[m]] into inv[a_rows[m]]
 void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s);
+size_t gemm_workspace_bytes(int rows, int K);
 void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parallel,
                       hipStream_t s);
 size_t attention_ws_bytes(int n_items);

@@ -90,6 +90,7 @@ struct nc_ctx {
   DevBuf<int32_t> lastrow;  // per stream: row of its last position in the latest pass
   DevBuf<float> xinv;       // inverse RMS of each pass row's residual
   DevBuf<float> aws;        // attention group states (decode path)
+  DevBuf<float> gws;        // quantised A operand of normed GEMMs with few rows
   DevBuf<float> hinv;       // inverse RMS of each stream's newest residual (hlast)
   DevBuf<uint8_t> dstage;   // per-step staged inputs
   void* spin = nullptr;     // pinned host side of the stage
@@ -127,7 +128,7 @@ nc_ctx::~nc_ctx() {
   if (dev >= 0) (void)hipSetDevice(dev);
   if (st) (void)hipStreamSynchronize(st);
   for (void* p : allocs) (void)hipFree(p);
-  DevBuf<float>* fb[] = {&aws, &xinv, &hinv, &amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
+  DevBuf<float>* fb[] = {&gws, &aws, &xinv, &hinv, &amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
                          &dbgp, &dbgpt};
   for (auto* q : fb) q->release();
   DevBuf<int32_t>* ib[] = {&uni, &nseen, &hist, &ncommit, &moded, &next_ctx, &keys, &kidx,
@@ -433,6 +434,23 @@ __global__ void copy_rows_kernel(const float* x, const float* xinv, const int32_
 // Appends a planned pass to the KV caches; leaves each row's final residual in x and each
 // stream's newest row in hlast.  Rows of one stream are consecutive positions spanning fewer than
 // `slide` positions (the ring holds ctx_len + slide entries, so no needed key is overwritten).
+// Workspace of a normed GEMM (its A operand, quantised, when it has few rows).
+static void gemm_ws(nc_ctx* c, GemmArgs& a) {
+  const size_t need = gemm_workspace_bytes(256, a.K);  // only GEMMs under 256 rows stage A
+  c->gws.alloc((need + 3) / 4);
+  a.a_ws = c->gws.p;
+  a.a_ws_bytes = c->gws.n * 4;
+}
+
+// Many-row bf16 / fp8 passes: the inverse RMS of every row once, ahead of a normed GEMM (the
+// wide tile kernel would otherwise recompute it in every column tile).  Same arithmetic as the
+// GEMMs' own computation.
+static void norm_rows(nc_ctx* c, GemmArgs& a, int n, int prec) {
+  if (n < 256 || prec == P_F32) return;
+  launch_row_rms(a, c->xinv.p, c->st);
+  a.inv = c->xinv.p;
+}
+
 void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = {}) {
   const int n = int(p.rows.size());
   if (!n) return;
@@ -470,7 +488,9 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     a.Hk = c->hk;
     a.hd = c->hd;
     a.ring = c->R;
+    gemm_ws(c, a);
     prof_begin(c, NC_K_QKV);
+    norm_rows(c, a, n, prec);
     launch_gemm(prec, A_NORM, E_QKV, a, c->st);
     prof_end(c, NC_K_QKV, gemm_bytes(a, A_NORM, E_QKV, prec, att), 2.0 * a.M * a.N * a.K);
     // attention
@@ -529,7 +549,9 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     gu.out_p = c->hb.p;
     gu.out_scale = L.sa_d;
     gu.out_amax = am ? am + 3 : nullptr;
+    gemm_ws(c, gu);
     prof_begin(c, NC_K_GATEUP);
+    norm_rows(c, gu, n, prec);
     launch_gemm(prec, A_NORM, E_GLU, gu, c->st);
     prof_end(c, NC_K_GATEUP, gemm_bytes(gu, A_NORM, E_GLU, prec, att), 2.0 * n * gu.N * gu.K);
     // down projection + residual
@@ -582,6 +604,7 @@ void run_lm_head(nc_ctx* c, const float* A, const float* Ainv, const int32_t* a_
   a.out_f32 = zout;
   a.ldo = c->V;
   a.inv = Ainv;
+  gemm_ws(c, a);
   const int prec = calib ? P_F32 : c->prec;
   prof_begin(c, NC_K_LMHEAD);
   launch_gemm(prec, A_NORM, E_STORE, a, c->st);
