@@ -172,17 +172,20 @@ def main():
         out = ctx.decode_stream(data, [len(s) for s in streams])
         td = time.perf_counter()
         torch.cuda.synchronize()
-        return data, bits, out, te - t0, td - te, st_enc
+        st_dec = ctx.stats()
+        return data, bits, out, te - t0, td - te, st_enc, st_dec
 
     for _ in range(args.warmup):
         step()
     ctx.profile(args.kernel)
-    t_enc = t_dec = 0.0
+    t_enc = t_dec = w_enc = w_dec = 0.0
     ok = True
     for _ in range(args.steps):
-        data, bits, out, te, td, st_enc = step()
+        data, bits, out, te, td, st_enc, st_dec = step()
         t_enc += te
         t_dec += td
+        w_enc += st_enc["wait_seconds"]
+        w_dec += st_dec["wait_seconds"]
         ok = ok and all(np.array_equal(a, b) for a, b in zip(out, streams))
     prof = ctx.profile_read()
     ctx.profile(None)
@@ -223,6 +226,7 @@ def main():
             "decode_tok_s": round(args.steps * n_tok / t_dec, 2),
             "bits_per_token": round(total_bits / n_tok, 5),
             "skip_rate": None, "roundtrip_exact": bool(ok),
+            "host_wait_frac": {"encode": round(w_enc / t_enc, 3), "decode": round(w_dec / t_dec, 3)},
             "roofline": roofline}
     dstat = ctx.stats()
     line["skip_rate"] = round(dstat["skipped"] / max(dstat["tokens"], 1), 4)

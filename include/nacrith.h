@@ -97,6 +97,7 @@ typedef struct nc_stats {
   double bits;               /* exact coded bits (sum over streams) */
   double ideal_bits;         /* sum -log2 p_i(t_i) of the float32 coding distributions */
   double seconds;            /* wall time of the call */
+  double wait_seconds;       /* part of it the host spent blocked on the device */
 } nc_stats;
 
 typedef struct nc_ctx nc_ctx;

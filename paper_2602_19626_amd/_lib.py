@@ -39,7 +39,7 @@ class NcProbe(C.Structure):
 class NcStats(C.Structure):
     _fields_ = [("tokens", C.c_uint64), ("llm_rows", C.c_uint64), ("skipped", C.c_uint64),
                 ("body_rows", C.c_uint64), ("bits", C.c_double), ("ideal_bits", C.c_double),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("wait_seconds", C.c_double)]
 
 
 class NcKstat(C.Structure):

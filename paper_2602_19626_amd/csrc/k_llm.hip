@@ -855,28 +855,34 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
 
 // ---- attention ------------------------------------------------------------------------------
 //
-// Keys of a query's window [s(pos), pos] are cut into 64-key chunks at fixed absolute positions
-// (4 MFMA blocks of 16), and chunks into groups of 16 (1,024 keys).  A chunk partial is one softmax
-// pass over its 64 keys:
-//   m = max score, p = 2^(score - m), l = sum p (fixed order), o = V^T P^T (4 chained MFMAs).
+// Keys of a query's window [s(pos), pos] are cut into 64-key chunks at fixed absolute positions,
+// chunks into quads of 4 (256 keys) and quads into groups of 4 (1,024 keys).  A chunk partial is
+// one softmax pass over its 64 keys:
+//   m = max score, p = 2^(score - m), l = sum p (fixed order), o = V^T P^T (chained MFMAs).
 // Partials are combined by the left fold
 //   (m, l, o) <- (M, l 2^(m - M) + l' 2^(m' - M), o 2^(m - M) + o' 2^(m' - M)),  M = max(m, m'),
-// first over the chunks of each group (from empty), then over the group results in order; the
-// output is o / l.  Chunks or groups outside a column's window are empty (-inf, 0, 0) and fold as a
-// no-op, so a column's result does not depend on the other columns of its launch.
+// at three levels, each from the empty state (-inf, 0, 0) and in order: the chunks of a quad, the
+// quads of a group, then the groups; the output is o / l.  Folding the empty state is exact in
+// either operand, so chunks outside a column's window drop out and a column's result does not
+// depend on the other columns of its launch, nor on which kernel computes it.
 // S^T = K Q^T puts keys on MFMA rows and (query, head) pairs on columns, so the probabilities
-// leave the QK MFMA in the B-operand layout of the 16x16x16 P*V MFMA (lane: column l%16, keys
-// 4(l/16)..+3) and no transpose is needed.
+// leave the QK MFMA in the B-operand layout of the P*V MFMA and no transpose is needed.  Within a
+// chunk, MFMA row r of block b holds key 16 (r / 4) + 4 b + r % 4: a lane's P*V operand then
+// covers 16 consecutive keys over the 4 blocks, so its V^T reads are contiguous.
 
 constexpr int KCH = 64;      // keys per chunk
-constexpr int GCH = 16;      // chunks per group
-constexpr int MAXG = 4;      // groups an item may span (window <= 2,048 keys + 15 query positions)
+constexpr int QCH = 4;       // chunks per quad
+constexpr int GQ = 4;        // quads per group
+constexpr int MAXQ = 12;     // quads an item may span (window <= 2,048 keys + 15 query positions)
 constexpr int HDMAX = 64;
-constexpr int DEC_WAVES = 16;
+constexpr int QSTATE = 2 + HDMAX / 4;  // floats per lane of a stored state: m, l, o[16]
 
 __device__ __forceinline__ int window_start(int pos, int L, int C) {
   return pos < L ? 0 : C * (1 + (pos - L) / C);
 }
+
+// key offset within its chunk of MFMA row r of block b
+__device__ __forceinline__ int chunk_key(int b, int r) { return (r >> 2) * 16 + b * 4 + (r & 3); }
 
 struct AttnCol {
   bool valid;
@@ -906,6 +912,24 @@ __device__ __forceinline__ void fold(ChunkState& a, const ChunkState& b, int nhb
   a.m = M;
 }
 
+// state of one lane <-> 18 floats (wave-interleaved: float i of lane l at i * 64 + l)
+__device__ __forceinline__ void state_put(float* dst, const ChunkState& st, int lane) {
+  dst[lane] = st.m;
+  dst[64 + lane] = st.l;
+#pragma unroll
+  for (int hb = 0; hb < HDMAX / 16; ++hb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[(2 + hb * 4 + j) * 64 + lane] = st.o[hb][j];
+}
+__device__ __forceinline__ void state_get(ChunkState& st, const float* src, int lane) {
+  st.m = src[lane];
+  st.l = src[64 + lane];
+#pragma unroll
+  for (int hb = 0; hb < HDMAX / 16; ++hb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st.o[hb][j] = src[(2 + hb * 4 + j) * 64 + lane];
+}
+
 template <int PA>
 struct QFrag {
   v8bf b[2];
@@ -921,21 +945,21 @@ __device__ __forceinline__ void load_q(QFrag<PA>& q, const AttnArgs& a, const At
     const uint16_t* Q = static_cast<const uint16_t*>(a.q);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      alignas(16) uint16_t t[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = s * 32 + grp * 8 + i;
-        t[i] = (c.valid && k < hd) ? Q[qbase + k] : uint16_t(0);
-      }
-      q.b[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<v4i*>(t));
+      const int k = s * 32 + grp * 8;
+      const v4i v = (c.valid && k < hd) ? *reinterpret_cast<const v4i*>(Q + qbase + k)
+                                        : v4i{0, 0, 0, 0};
+      q.b[s] = __builtin_bit_cast(v8bf, v);
     }
   } else {
     // step s, lane group g: hd entry 16 g + s (the same mapping is used for K)
     const float* Q = static_cast<const float*>(a.q);
 #pragma unroll
-    for (int s = 0; s < HDMAX / 4; ++s) {
-      const int k = 16 * grp + s;
-      q.f[s] = (c.valid && k < hd) ? Q[qbase + k] : 0.f;
+    for (int qd = 0; qd < 4; ++qd) {
+      const int k = 16 * grp + 4 * qd;
+      const v4f v = (c.valid && k < hd) ? *reinterpret_cast<const v4f*>(Q + qbase + k)
+                                        : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) q.f[4 * qd + e] = v[e];
     }
   }
 }
@@ -948,7 +972,7 @@ __device__ __forceinline__ void chunk_softmax(v4f (&st)[4], const AttnArgs& a, c
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int key = key0 + b * 16 + grp * 4 + j;
+      const int key = key0 + chunk_key(b, grp * 4 + j);
       const bool ok = c.valid && key >= c.cs && key <= c.pos;
       st[b][j] = ok ? st[b][j] * a.scale_log2 : -INFINITY;
       mx = fmaxf(mx, st[b][j]);
@@ -976,6 +1000,8 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
   const int hd = a.hd, nhb = hd / 16;
   const long long sbase = (long long)it.stream * a.kv_stride + (long long)it.kvh * a.ring * hd;
   const int key0 = chunk * KCH;
+  // V^T operand of this lane: keys key0 + 16 grp .. + 15 (never wrapping: ring % 16 == 0)
+  const int vslot = (key0 + 16 * grp) % a.ring;
   v4f st[4];
   ChunkState r;
 #pragma unroll
@@ -985,22 +1011,23 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
     const uint16_t* Vt = static_cast<const uint16_t*>(a.vt_cache);
     // K and V^T fragments of the 4 blocks, all loads in flight together
     v4i kf[4][2];
-    v4s vf[4][HDMAX / 16];
+    v4i vf[HDMAX / 16][2];  // 16 keys per lane per hd block
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const long long ks = sbase + (long long)((key0 + b * 16 + col) % a.ring) * hd;
+      const long long ks = sbase + (long long)((key0 + chunk_key(b, col)) % a.ring) * hd;
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int k = s * 32 + grp * 8;
         kf[b][s] = k < hd ? *reinterpret_cast<const v4i*>(Kc + ks + k) : v4i{0, 0, 0, 0};
       }
-      const int slot = (key0 + b * 16 + grp * 4) % a.ring;
-#pragma unroll
-      for (int hb = 0; hb < HDMAX / 16; ++hb)
-        vf[b][hb] = hb < nhb ? *reinterpret_cast<const v4s*>(
-                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + slot)
-                             : v4s{0, 0, 0, 0};
     }
+#pragma unroll
+    for (int hb = 0; hb < HDMAX / 16; ++hb)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        vf[hb][h] = hb < nhb ? *reinterpret_cast<const v4i*>(
+                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + vslot + 8 * h)
+                             : v4i{0, 0, 0, 0};
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       st[b] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1018,14 +1045,28 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
       for (int j = 0; j < 4; ++j) pb[j] = short(f2bf(st[b][j]));
 #pragma unroll
       for (int hb = 0; hb < HDMAX / 16; ++hb)
-        if (hb < nhb) r.o[hb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vf[b][hb], pb, r.o[hb], 0, 0, 0);
+        if (hb < nhb) {
+          // keys 4 b .. 4 b + 3 of the lane's 16: dwords 2 (b % 2) .. + 1 of half b / 2
+          const v4i w = vf[hb][b >> 1];
+          const v4s va = __builtin_bit_cast(v4s, (b & 1) ? int2{w[2], w[3]} : int2{w[0], w[1]});
+          r.o[hb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(va, pb, r.o[hb], 0, 0, 0);
+        }
     }
   } else {
     const float* Kc = static_cast<const float*>(a.k_cache);
     const float* Vt = static_cast<const float*>(a.vt_cache);
+    // V^T fragments requested first so their latency overlaps the QK MFMAs
+    v4f vf[HDMAX / 16][4];
+#pragma unroll
+    for (int hb = 0; hb < HDMAX / 16; ++hb)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        vf[hb][b] = hb < nhb ? *reinterpret_cast<const v4f*>(
+                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + vslot + 4 * b)
+                             : v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const long long ks = sbase + (long long)((key0 + b * 16 + col) % a.ring) * hd;
+      const long long ks = sbase + (long long)((key0 + chunk_key(b, col)) % a.ring) * hd;
       float kf[HDMAX / 4];
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
@@ -1039,17 +1080,6 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
       for (int s = 0; s < HDMAX / 4; ++s)
         st[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kf[s], q.f[s], st[b], 0, 0, 0);
     }
-    // V^T fragments requested before the softmax so their latency overlaps it
-    v4f vf[4][HDMAX / 16];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int slot = (key0 + b * 16 + grp * 4) % a.ring;
-#pragma unroll
-      for (int hb = 0; hb < HDMAX / 16; ++hb)
-        vf[b][hb] = hb < nhb ? *reinterpret_cast<const v4f*>(
-                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + slot)
-                             : v4f{0.f, 0.f, 0.f, 0.f};
-    }
     chunk_softmax(st, a, c, key0, grp, r.m, r.l);
 #pragma unroll
     for (int b = 0; b < 4; ++b)
@@ -1058,7 +1088,7 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
         if (hb < nhb)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            r.o[hb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[b][hb][j], st[b][j], r.o[hb], 0, 0, 0);
+            r.o[hb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[hb][b][j], st[b][j], r.o[hb], 0, 0, 0);
   }
   return r;
 }
@@ -1115,7 +1145,7 @@ __device__ __forceinline__ float attn_store(const AttnArgs& a, const AttnItem& i
   return omax;
 }
 
-// Many items (prefill): one wave per item; chunks folded per group, groups folded in order.
+// Many items (prefill): one wave per item, the three fold levels in registers.
 template <int PA, int PO>
 __global__ __launch_bounds__(256) void attention_seq_kernel(const AttnArgs a) {
   const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
@@ -1128,12 +1158,18 @@ __global__ __launch_bounds__(256) void attention_seq_kernel(const AttnArgs a) {
   load_q<PA>(q, a, c, grp);
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);
-  ChunkState run, gs;
+  ChunkState run, gs, qs;
   state_empty(run);
+  constexpr int GCH = QCH * GQ;
   for (int g0 = (c_lo / GCH) * GCH; g0 <= c_hi; g0 += GCH) {
     state_empty(gs);
-    for (int ch = max(g0, c_lo); ch <= min(g0 + GCH - 1, c_hi); ++ch)
-      fold(gs, chunk_partial<PA>(a, it, c, q, ch, col, grp), nhb);
+    for (int q0 = g0; q0 < g0 + GCH; q0 += QCH) {
+      if (q0 + QCH - 1 < c_lo || q0 > c_hi) continue;
+      state_empty(qs);
+      for (int ch = max(q0, c_lo); ch <= min(q0 + QCH - 1, c_hi); ++ch)
+        fold(qs, chunk_partial<PA>(a, it, c, q, ch, col, grp), nhb);
+      fold(gs, qs, nhb);
+    }
     fold(run, gs, nhb);
   }
   float omax = attn_store<PO>(a, it, run, col, grp);
@@ -1143,83 +1179,58 @@ __global__ __launch_bounds__(256) void attention_seq_kernel(const AttnArgs a) {
   }
 }
 
-// Few items (decode): one workgroup per (item, group); wave w computes chunk group*16 + w, wave 0
-// folds the group's partials in order and writes the group state.
+// Few items (decode), first kernel: one 4-wave workgroup per (item, quad); wave w computes chunk
+// 4 Q + w, wave 0 folds the quad in order and stores its state.
 template <int PA>
-__global__ __launch_bounds__(64 * DEC_WAVES) void attention_group_kernel(const AttnArgs a) {
-  __shared__ float pm[DEC_WAVES][16], pl[DEC_WAVES][16];
-  __shared__ float po[DEC_WAVES][HDMAX / 16][4][64];
+__global__ __launch_bounds__(256) void attention_quad_kernel(const AttnArgs a) {
+  __shared__ float part[QCH][QSTATE * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int item = blockIdx.x, gi = blockIdx.y;
+  const int item = blockIdx.x, qi = blockIdx.y;
   const AttnItem it = a.items[item];
-  const AttnCol c = attn_col(a, it, col);
-  const int nhb = a.hd / 16;
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);
-  const int g0 = (c_lo / GCH + gi) * GCH;
-  const int ch = g0 + wave;
-  const bool active = ch >= c_lo && ch <= c_hi;
-  if (active) {
+  const int q0 = (c_lo / QCH + qi) * QCH;
+  if (q0 > c_hi) return;  // beyond the item: its fold never reads this quad
+  const AttnCol c = attn_col(a, it, col);
+  const int nhb = a.hd / 16;
+  const int ch = q0 + wave;
+  if (ch >= c_lo && ch <= c_hi) {
     QFrag<PA> q;
     load_q<PA>(q, a, c, grp);
-    const ChunkState p = chunk_partial<PA>(a, it, c, q, ch, col, grp);
-    if (grp == 0) {
-      pm[wave][col] = p.m;
-      pl[wave][col] = p.l;
-    }
-#pragma unroll
-    for (int hb = 0; hb < HDMAX / 16; ++hb)
-      if (hb < nhb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) po[wave][hb][j][lane] = p.o[hb][j];
+    state_put(part[wave], chunk_partial<PA>(a, it, c, q, ch, col, grp), lane);
   }
   __syncthreads();
   if (wave != 0) return;
-  ChunkState gs;
-  state_empty(gs);
-  for (int w = 0; w < DEC_WAVES; ++w) {
-    if (!(g0 + w >= c_lo && g0 + w <= c_hi)) continue;
-    ChunkState p;
-    p.m = pm[w][col];
-    p.l = pl[w][col];
-#pragma unroll
-    for (int hb = 0; hb < HDMAX / 16; ++hb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) p.o[hb][j] = hb < nhb ? po[w][hb][j][lane] : 0.f;
-    fold(gs, p, nhb);
+  ChunkState qs, p;
+  state_empty(qs);
+  for (int w = 0; w < QCH; ++w) {
+    if (q0 + w < c_lo || q0 + w > c_hi) continue;
+    state_get(p, part[w], lane);
+    fold(qs, p, nhb);
   }
-  // group state: [item][gi][lane][2 + 16]
-  float* dst = a.ws + ((long long)item * MAXG + gi) * 64 * 18 + lane * 18;
-  dst[0] = gs.m;
-  dst[1] = gs.l;
-#pragma unroll
-  for (int hb = 0; hb < HDMAX / 16; ++hb)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dst[2 + hb * 4 + j] = gs.o[hb][j];
+  state_put(a.ws + ((long long)item * MAXQ + qi) * QSTATE * 64, qs, lane);
 }
 
+// Few items, second kernel: quads -> groups -> output, one wave per item.
 template <int PO>
-__global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a, int ngroups) {
+__global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a) {
   const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
   const int item = blockIdx.x;
   const AttnItem it = a.items[item];
   const int nhb = a.hd / 16;
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);
-  const int ng = c_hi / GCH - c_lo / GCH + 1;
-  ChunkState run;
+  const int qlo = c_lo / QCH, qhi = c_hi / QCH;
+  ChunkState run, gs, p;
   state_empty(run);
-  for (int gi = 0; gi < ng && gi < ngroups; ++gi) {
-    const float* src = a.ws + ((long long)item * MAXG + gi) * 64 * 18 + lane * 18;
-    ChunkState p;
-    p.m = src[0];
-    p.l = src[1];
-#pragma unroll
-    for (int hb = 0; hb < HDMAX / 16; ++hb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) p.o[hb][j] = src[2 + hb * 4 + j];
-    fold(run, p, nhb);
+  for (int g0 = (qlo / GQ) * GQ; g0 <= qhi; g0 += GQ) {
+    state_empty(gs);
+    for (int qq = max(g0, qlo); qq <= min(g0 + GQ - 1, qhi); ++qq) {
+      state_get(p, a.ws + ((long long)item * MAXQ + (qq - qlo)) * QSTATE * 64, lane);
+      fold(gs, p, nhb);
+    }
+    fold(run, gs, nhb);
   }
   float omax = attn_store<PO>(a, it, run, col, grp);
   if (a.out_amax) {
@@ -1368,36 +1379,37 @@ void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s)
   NC_HIP(hipGetLastError());
 }
 
-// Groups an item can span: its keys run from the window start of its first query to its last
+// Quads an item can span: its keys run from the window start of its first query to its last
 // query, at most ctx_len + 15 keys (a window holds at most ctx_len keys, an item at most 16
 // query positions), i.e. at most nch chunks at any alignment.
-static int attention_groups(int ctx_len) {
+static int attention_quads(int ctx_len) {
   const int nch = (ctx_len + 15 + KCH - 1) / KCH + 1;
-  return (nch - 1 + GCH - 1) / GCH + 1;
+  return (nch - 1 + QCH - 1) / QCH + 1;
 }
 
 template <int PA, int PO>
 static void attn_go(const AttnArgs& a, bool parallel, hipStream_t s) {
   if (parallel) {
-    const int ng = attention_groups(a.ctx_len);
-    hipLaunchKernelGGL((attention_group_kernel<PA>), dim3(a.n_items, ng), dim3(64 * DEC_WAVES), 0,
-                       s, a);
-    hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64), 0, s, a, ng);
+    const int nq = attention_quads(a.ctx_len);
+    hipLaunchKernelGGL((attention_quad_kernel<PA>), dim3(a.n_items, nq), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64), 0, s, a);
   } else {
     hipLaunchKernelGGL((attention_seq_kernel<PA, PO>), dim3((a.n_items + 3) / 4), dim3(256), 0, s,
                        a);
   }
 }
 
-size_t attention_ws_bytes(int n_items) { return size_t(n_items) * MAXG * 64 * 18 * sizeof(float); }
+size_t attention_ws_bytes(int n_items) {
+  return size_t(n_items) * MAXQ * QSTATE * 64 * sizeof(float);
+}
 
-// parallel: a workgroup per (item, 1,024-key group) and a fold kernel (few items, decode);
+// parallel: a workgroup per (item, quad of chunks) and a fold kernel (few items, decode);
 // otherwise one wave per item (prefill).  Both produce the same bits.
 void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parallel,
                       hipStream_t s) {
   if (a.n_items <= 0) return;
   NC_CHECK(a.hd % 16 == 0 && a.hd <= HDMAX, NC_E_INVALID, "head_dim must be 16..64, x16");
-  NC_CHECK(attention_groups(a.ctx_len) <= MAXG, NC_E_INVALID, "context window too large");
+  NC_CHECK(attention_quads(a.ctx_len) <= MAXQ, NC_E_INVALID, "context window too large");
   NC_CHECK(a.ring % 16 == 0, NC_E_INVALID, "ring must be a multiple of 16");
   if (parallel)
     NC_CHECK(a.ws && a.ws_bytes >= attention_ws_bytes(a.n_items), NC_E_INVALID,

@@ -203,7 +203,10 @@ void prof_flush(nc_ctx* c) {
 }
 
 void sync(nc_ctx* c) {
+  const auto t0 = std::chrono::steady_clock::now();
   NC_HIP(hipStreamSynchronize(c->st));
+  c->stats.wait_seconds +=
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   prof_flush(c);
 }
 
