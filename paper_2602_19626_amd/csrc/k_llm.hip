@@ -109,21 +109,39 @@ __device__ __forceinline__ void atomic_max_abs(float* p, float v) {
 //     f32 16x16x4:            16 steps, step t / lane group g consumes k = 16 g + t,
 //     bf16 / fp8 16x16x32:     2 steps, step t / lane group g consumes k = 32 t + 8 g .. + 7,
 //   with entries beyond K read as zero.
-// The tile kernels (many rows) sum the parts as they walk K; the split kernel (few rows) computes
-// each part in its own wave and the workgroup adds the parts in order.  Both then apply the same
-// epilogue function, so a row's outputs do not depend on how many rows are in the launch.
+// A normed GEMM (A_NORM) then multiplies by deq (FP8) and by the row's RMSNorm scale, in that
+// order.  The tile kernels (many rows) sum the parts as they walk K; the split kernel (few rows)
+// computes each part in its own wave and the workgroup adds the parts in order.  All apply the
+// same epilogue functions, so a row's outputs do not depend on how many rows are in the launch.
 
 constexpr int KP = 64;
 
-// 1 / sqrt(mean(x^2) + eps) of one row: lanes stride over K, then a fixed xor-tree reduction.
-__device__ __forceinline__ float row_inv_rms(const float* x, int K, float eps, int lane) {
-  float ss = 0.f;
-  for (int k = lane; k < K; k += 64) {
-    const float v = x[k];
-    ss += v * v;
-  }
-  ss = wave_sum_f(ss);
-  return 1.0f / sqrtf(ss / float(K) + eps);
+// RMSNorm scale of a row, 1 / sqrt(mean(x^2) + eps), from block sums of squares.  Whatever writes
+// a residual row x (embedding, residual epilogues) also writes, for each 16-column block b,
+// ssq[b] = sum of x^2 over the block by one fixed tree (block_ssq16); the scale adds the block
+// sums in block order.  Prefill and decode kernels therefore derive bitwise equal scales.
+
+// Block sum of squares of 16 values held by 16 consecutive lanes (lane % 16 = column); every lane
+// of the group returns the same bits.
+__device__ __forceinline__ float block_ssq16(float x) {
+  float v = x * x;
+  v += __shfl_xor(v, 8, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
+__device__ __forceinline__ float inv_from_ssq(const float* ssq, int K, float eps) {
+  const int nb = K / 16;
+  float t = 0.f;
+  for (int b = 0; b < nb; ++b) t += ssq[b];
+  return 1.0f / sqrtf(t / float(K) + eps);
+}
+
+// the scale of A row ar of a normed GEMM
+__device__ __forceinline__ float a_row_inv(const GemmArgs& a, int ar) {
+  return a.inv ? a.inv[ar] : inv_from_ssq(a.ssq + (long long)ar * (a.K / 16), a.K, a.eps);
 }
 
 // ---- epilogue emitters ----
@@ -208,19 +226,6 @@ struct Frag<P_F32> {
       for (int e = 0; e < 4; ++e) f[4 * q + e] = v[e];
     }
   }
-  template <class N4>
-  __device__ static void load_norm(T& f, N4&& norm, int k0, int g, float, float& amax) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float v[4];
-      norm(k0 + 16 * g + 4 * q, v);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        f[4 * q + e] = v[e];
-        amax = fmaxf(amax, fabsf(v[e]));
-      }
-    }
-  }
   __device__ static void mma(v4f& acc, const T& a, const T& b) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[t], acc, 0, 0, 0);
@@ -239,22 +244,6 @@ struct Frag<P_BF16> {
     for (int t = 0; t < 2; ++t) {
       const int k = k0 + 32 * t + 8 * g;
       f[t] = k < K ? *reinterpret_cast<const v4i*>(row + (long long)k * 2) : v4i{0, 0, 0, 0};
-    }
-  }
-  template <class N4>
-  __device__ static void load_norm(T& f, N4&& norm, int k0, int g, float inv_scale, float& amax) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      alignas(16) uint8_t b[16];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        float v[4];
-        norm(k0 + 32 * t + 8 * g + 4 * h, v);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) amax = fmaxf(amax, fabsf(v[e]));
-        PT<P_BF16>::put4(b + 8 * h, v, inv_scale);
-      }
-      f[t] = *reinterpret_cast<const v4i*>(b);
     }
   }
   __device__ static void mma(v4f& acc, const T& a, const T& b) {
@@ -279,22 +268,6 @@ struct Frag<P_FP8> {
       f[t] = k < K ? *reinterpret_cast<const long*>(row + k) : 0;
     }
   }
-  template <class N4>
-  __device__ static void load_norm(T& f, N4&& norm, int k0, int g, float inv_scale, float& amax) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      alignas(8) uint8_t b[8];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        float v[4];
-        norm(k0 + 32 * t + 8 * g + 4 * h, v);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) amax = fmaxf(amax, fabsf(v[e]));
-        PT<P_FP8>::put4(b + 4 * h, v, inv_scale);
-      }
-      f[t] = *reinterpret_cast<const long*>(b);
-    }
-  }
   __device__ static void mma(v4f& acc, const T& a, const T& b) {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -302,17 +275,26 @@ struct Frag<P_FP8> {
   }
 };
 
-// Normalised A values x * inv * gain for 4 consecutive k (the operand value before rounding).
-__device__ __forceinline__ void norm4(const float* xrow, const float* gain, int k, int K,
-                                      float inv, float (&v)[4]) {
-  if (k < K) {
-    const v4f x = *reinterpret_cast<const v4f*>(xrow + k);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = x[i] * inv * gain[k + i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = 0.f;
-  }
+// Residual epilogue of element (m, n) after x[m][n] was updated to xn: the block sum of squares of
+// row m over the 16-column block of n (held by the 16 lanes with lane % 16 = column), and the
+// next normed GEMM's operand quantise(xn * y_gain[n]).  Every lane of the wave must call this;
+// lanes with ok == false pass xn = 0 and store nothing.  Returns |xn * y_gain[n]|.
+template <int P>
+__device__ __forceinline__ float resid_out(const GemmArgs& a, int m, int n, float xn, int c,
+                                           bool ok) {
+  const float sq = block_ssq16(xn);
+  if (!ok) return 0.f;
+  if (a.ssq_out && c == 0) a.ssq_out[(long long)m * (a.N / 16) + n / 16] = sq;
+  if (!a.y_out) return 0.f;
+  const float yv = xn * a.y_gain[n];
+  PT<P>::store(a.y_out, (long long)m * a.N + n, yv, a.y_inv_scale);
+  return fabsf(yv);
+}
+
+__device__ __forceinline__ void amax_flush(float* dst, float v, int lane) {
+  if (!dst) return;
+  v = wave_max_f(v);
+  if (lane == 0) atomic_max_abs(dst, v);
 }
 
 // ---- tile kernel (many rows): LDS-staged 64-wide K parts ----
@@ -340,15 +322,8 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
     s_arow[r] = m < a.M ? (a.a_rows ? a.a_rows[m] : m) : -1;
   }
   __syncthreads();
-  if constexpr (AM == A_NORM) {
-    const float* X = static_cast<const float*>(a.A);
-    for (int r = wave; r < BM; r += NT / 64) {
-      const int ar = s_arow[r];
-      const float inv = ar >= 0 ? row_inv_rms(X + (long long)ar * K, K, a.eps, lane) : 0.f;
-      if (lane == 0) s_inv[r] = inv;
-    }
-    __syncthreads();
-  }
+  for (int r = tid; r < BM; r += NT)
+    s_inv[r] = (AM == A_NORM && s_arow[r] >= 0) ? a_row_inv(a, s_arow[r]) : 1.f;
 
   v4f tot[RB][CB];
 #pragma unroll
@@ -356,43 +331,25 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
 #pragma unroll
     for (int j = 0; j < CB; ++j) tot[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  float amax = 0.f;
-  const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
   const int fr = lane & 15, fg = lane >> 4;
-
+  const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
+  const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
   for (int k0 = 0; k0 < K; k0 += KP) {
-    if constexpr (AM == A_NORM) {
-      const float* X = static_cast<const float*>(a.A);
-      for (int c = tid; c < BM * (KP / 4); c += NT) {
-        const int r = c / (KP / 4), kc = c % (KP / 4);
-        const int ar = s_arow[r];
-        float v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (ar >= 0) norm4(X + (long long)ar * K, a.gain, k0 + kc * 4, K, s_inv[r], v);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(v[i]));
-        PT<P>::put4(lds_a + r * ROWB + kc * 4 * ES, v, a_inv);
-      }
-    } else {
-      const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
-      for (int c = tid; c < BM * CPR; c += NT) {
-        const int r = c / CPR, kc = c % CPR;
-        const int k = k0 + kc * (16 / ES);
-        const int ar = s_arow[r];
-        v4i v = {0, 0, 0, 0};
-        if (ar >= 0 && k < K) v = *reinterpret_cast<const v4i*>(A8 + ((long long)ar * K + k) * ES);
-        *reinterpret_cast<v4i*>(lds_a + r * ROWB + kc * 16) = v;
-      }
+    for (int c = tid; c < BM * CPR; c += NT) {
+      const int r = c / CPR, kc = c % CPR;
+      const int k = k0 + kc * (16 / ES);
+      const int ar = s_arow[r];
+      v4i v = {0, 0, 0, 0};
+      if (ar >= 0 && k < K) v = *reinterpret_cast<const v4i*>(A8 + ((long long)ar * K + k) * ES);
+      *reinterpret_cast<v4i*>(lds_a + r * ROWB + kc * 16) = v;
     }
-    {
-      const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
-      for (int c = tid; c < BN * CPR; c += NT) {
-        const int r = c / CPR, kc = c % CPR;
-        const int k = k0 + kc * (16 / ES);
-        const int n = n0 + r;
-        v4i v = {0, 0, 0, 0};
-        if (n < a.N && k < K) v = *reinterpret_cast<const v4i*>(W8 + ((long long)n * K + k) * ES);
-        *reinterpret_cast<v4i*>(lds_b + r * ROWB + kc * 16) = v;
-      }
+    for (int c = tid; c < BN * CPR; c += NT) {
+      const int r = c / CPR, kc = c % CPR;
+      const int k = k0 + kc * (16 / ES);
+      const int n = n0 + r;
+      v4i v = {0, 0, 0, 0};
+      if (n < a.N && k < K) v = *reinterpret_cast<const v4i*>(W8 + ((long long)n * K + k) * ES);
+      *reinterpret_cast<v4i*>(lds_b + r * ROWB + kc * 16) = v;
     }
     __syncthreads();
     typename Frag<P>::T af[RB], bf[CB];
@@ -410,15 +367,16 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
       }
     __syncthreads();
   }
-  if (a.a_amax) {
-    amax = wave_max_f(amax);
-    if (lane == 0) atomic_max_abs(a.a_amax, amax);
-  }
 
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
   constexpr int PATT = P == P_F32 ? P_F32 : P_BF16;
+  // output value of accumulator (i, j, e): (sum of parts) * deq * row scale
+  auto val = [&](int i, int j, int e) {
+    return tot[i][j][e] * deq * s_inv[wm * WM + i * 16 + fg * 4 + e];
+  };
 
   if constexpr (EPI == E_STORE || EPI == E_RESID) {
+    float ymax = 0.f;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -427,14 +385,20 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
         for (int e = 0; e < 4; ++e) {
           const int m = m0 + wm * WM + i * 16 + fg * 4 + e;
           const int n = n0 + wn * WN + j * 16 + fr;
-          if (m < a.M && n < a.N) {
-            float* o = a.out_f32 + (long long)m * a.ldo + n;
-            if constexpr (EPI == E_RESID)
-              *o += tot[i][j][e] * deq;
-            else
-              *o = tot[i][j][e] * deq;
+          const bool ok = m < a.M && n < a.N;
+          if constexpr (EPI == E_RESID) {
+            float xn = 0.f;
+            if (ok) {
+              float* o = a.out_f32 + (long long)m * a.ldo + n;
+              xn = *o + val(i, j, e);
+              *o = xn;
+            }
+            ymax = fmaxf(ymax, resid_out<P>(a, m, n, xn, fr, ok));
+          } else if (ok) {
+            a.out_f32[(long long)m * a.ldo + n] = val(i, j, e);
           }
         }
+    if constexpr (EPI == E_RESID) amax_flush(a.y_amax, ymax, lane);
   } else if constexpr (EPI == E_GLU) {
     // W rows are interleaved in 16-row groups (gate, up, gate, up, ...)
     float omax = 0.f;
@@ -448,12 +412,9 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
           const int nb = n0 + wn * WN + j * 16;
           const int col = (nb / 32) * 16 + fr;
           if (m < a.M && col < a.N / 2)
-            omax = fmaxf(omax, emit_glu<P>(a, m, col, tot[i][j][e] * deq, tot[i][j + 1][e] * deq));
+            omax = fmaxf(omax, emit_glu<P>(a, m, col, val(i, j, e), val(i, j + 1, e)));
         }
-    if (a.out_amax) {
-      omax = wave_max_f(omax);
-      if (lane == 0) atomic_max_abs(a.out_amax, omax);
-    }
+    amax_flush(a.out_amax, omax, lane);
   } else if constexpr (EPI == E_QKV) {
     __shared__ float ct[BM][BN + 1];
 #pragma unroll
@@ -462,7 +423,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
       for (int j = 0; j < CB; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          ct[wm * WM + i * 16 + fg * 4 + e][wn * WN + j * 16 + fr] = tot[i][j][e] * deq;
+          ct[wm * WM + i * 16 + fg * 4 + e][wn * WN + j * 16 + fr] = val(i, j, e);
     __syncthreads();
     const int nqk = (a.Hq + a.Hk) * a.hd;
     for (int c = tid; c < BM * BN; c += NT) {
@@ -488,14 +449,12 @@ constexpr int WBM = 128, WBN = 128, WTHREADS = 256;
 
 template <int P, int AM, int EPI>
 __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a, int tiles_m,
-                                                             int tiles_n) {
+                                                                int tiles_n) {
   constexpr int ES = PT<P>::ES;
   constexpr int ROWB = KP * ES + 16;
   constexpr int TILEB = (WBM + WBN) * ROWB;
-  constexpr int CPR = KP * ES / 16;                     // 16-byte chunks per staged row
-  constexpr int NB16 = WBN * CPR / WTHREADS;            // W chunks per thread
-  constexpr int NA16 = WBM * CPR / WTHREADS;            // A chunks per thread (A_DIRECT)
-  constexpr int NAF = WBM * (KP / 4) / WTHREADS;        // float4 A chunks per thread (A_NORM)
+  constexpr int CPR = KP * ES / 16;           // 16-byte chunks per staged row
+  constexpr int NB16 = WBN * CPR / WTHREADS;  // chunks per thread (A and W alike)
   __shared__ __align__(16) uint8_t lds[2 * TILEB];
   __shared__ float s_inv[WBM];
   __shared__ int s_arow[WBM];
@@ -516,83 +475,31 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
     s_arow[r] = m < a.M ? (a.a_rows ? a.a_rows[m] : m) : -1;
   }
   __syncthreads();
-  if constexpr (AM == A_NORM) {
-    const float* X = static_cast<const float*>(a.A);
-    for (int r = wave; r < WBM; r += WTHREADS / 64) {
-      const int ar = s_arow[r];
-      float v = 0.f;
-      if (ar >= 0) v = a.inv ? a.inv[ar] : row_inv_rms(X + (long long)ar * K, K, a.eps, lane);
-      if (lane == 0) s_inv[r] = v;
-    }
-    __syncthreads();
-  }
+  for (int r = tid; r < WBM; r += WTHREADS)
+    s_inv[r] = (AM == A_NORM && s_arow[r] >= 0) ? a_row_inv(a, s_arow[r]) : 1.f;
 
   // global -> register staging of one K part
-  v4f xa[AM == A_NORM ? NAF : 1];
-  v4f ga;
-  v4i ra[AM == A_NORM ? 1 : NA16];
-  v4i rb[NB16];
+  v4i ra[NB16], rb[NB16];
+  const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
   const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
   auto fetch = [&](int k0) {
-    if constexpr (AM == A_NORM) {
-      const float* X = static_cast<const float*>(a.A);
-      const int kc = tid % (KP / 4), k = k0 + kc * 4;  // fixed per thread
-      ga = k < K ? *reinterpret_cast<const v4f*>(a.gain + k) : v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int u = 0; u < NAF; ++u) {
-        const int r = tid / (KP / 4) + u * (WTHREADS / (KP / 4));
-        const int ar = s_arow[r];
-        xa[u] = (ar >= 0 && k < K) ? *reinterpret_cast<const v4f*>(X + (long long)ar * K + k)
-                                   : v4f{0.f, 0.f, 0.f, 0.f};
-      }
-    } else {
-      const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
-#pragma unroll
-      for (int u = 0; u < NA16; ++u) {
-        const int c = tid + u * WTHREADS, r = c / CPR, k = k0 + (c % CPR) * (16 / ES);
-        const int ar = s_arow[r];
-        ra[u] = (ar >= 0 && k < K) ? *reinterpret_cast<const v4i*>(A8 + ((long long)ar * K + k) * ES)
-                                   : v4i{0, 0, 0, 0};
-      }
-    }
 #pragma unroll
     for (int u = 0; u < NB16; ++u) {
       const int c = tid + u * WTHREADS, r = c / CPR, k = k0 + (c % CPR) * (16 / ES);
+      const int ar = s_arow[r];
+      ra[u] = (ar >= 0 && k < K) ? *reinterpret_cast<const v4i*>(A8 + ((long long)ar * K + k) * ES)
+                                 : v4i{0, 0, 0, 0};
       const int n = n0 + r;
       rb[u] = (n < a.N && k < K) ? *reinterpret_cast<const v4i*>(W8 + ((long long)n * K + k) * ES)
                                  : v4i{0, 0, 0, 0};
     }
   };
-  float amax = 0.f;
-  const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
   auto stage = [&](uint8_t* buf) {
-    uint8_t* la = buf;
-    uint8_t* lb = buf + WBM * ROWB;
-    if constexpr (AM == A_NORM) {
-      const int kc = tid % (KP / 4);
-#pragma unroll
-      for (int u = 0; u < NAF; ++u) {
-        const int r = tid / (KP / 4) + u * (WTHREADS / (KP / 4));
-        const float iv = s_inv[r];
-        float v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          v[i] = xa[u][i] * iv * ga[i];  // the same expression as norm4
-          amax = fmaxf(amax, fabsf(v[i]));
-        }
-        PT<P>::put4(la + r * ROWB + kc * 4 * ES, v, a_inv);
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < NA16; ++u) {
-        const int c = tid + u * WTHREADS;
-        *reinterpret_cast<v4i*>(la + (c / CPR) * ROWB + (c % CPR) * 16) = ra[u];
-      }
-    }
 #pragma unroll
     for (int u = 0; u < NB16; ++u) {
       const int c = tid + u * WTHREADS;
-      *reinterpret_cast<v4i*>(lb + (c / CPR) * ROWB + (c % CPR) * 16) = rb[u];
+      *reinterpret_cast<v4i*>(buf + (c / CPR) * ROWB + (c % CPR) * 16) = ra[u];
+      *reinterpret_cast<v4i*>(buf + WBM * ROWB + (c / CPR) * ROWB + (c % CPR) * 16) = rb[u];
     }
   };
 
@@ -626,31 +533,37 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
     if (s + 1 < S) stage(lds + ((s + 1) & 1) * TILEB);
     __syncthreads();
   }
-  if (a.a_amax) {
-    amax = wave_max_f(amax);
-    if (lane == 0) atomic_max_abs(a.a_amax, amax);
-  }
 
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
   const int mw = m0 + wm * 64, nw = n0 + wn * 64;
+  auto val = [&](int i, int j, int e) {
+    return tot[i][j][e] * deq * s_inv[wm * 64 + i * 16 + fg * 4 + e];
+  };
   if constexpr (EPI == E_STORE || EPI == E_RESID) {
+    float ymax = 0.f;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int m = mw + i * 16 + fg * 4 + e;
-        if (m >= a.M) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int n = nw + j * 16 + fr;
-          if (n >= a.N) continue;
-          float* o = a.out_f32 + (long long)m * a.ldo + n;
-          if constexpr (EPI == E_RESID)
-            *o += tot[i][j][e] * deq;
-          else
-            *o = tot[i][j][e] * deq;
+          const bool ok = m < a.M && n < a.N;
+          if constexpr (EPI == E_RESID) {
+            float xn = 0.f;
+            if (ok) {
+              float* o = a.out_f32 + (long long)m * a.ldo + n;
+              xn = *o + val(i, j, e);
+              *o = xn;
+            }
+            ymax = fmaxf(ymax, resid_out<P>(a, m, n, xn, fr, ok));
+          } else if (ok) {
+            a.out_f32[(long long)m * a.ldo + n] = val(i, j, e);
+          }
         }
       }
+    if constexpr (EPI == E_RESID) amax_flush(a.y_amax, ymax, lane);
   } else if constexpr (EPI == E_GLU) {
     float omax = 0.f;
 #pragma unroll
@@ -662,14 +575,10 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
 #pragma unroll
         for (int j = 0; j < 4; j += 2) {
           const int col = ((nw + j * 16) / 32) * 16 + fr;
-          if (col < a.N / 2)
-            omax = fmaxf(omax, emit_glu<P>(a, m, col, tot[i][j][e] * deq, tot[i][j + 1][e] * deq));
+          if (col < a.N / 2) omax = fmaxf(omax, emit_glu<P>(a, m, col, val(i, j, e), val(i, j + 1, e)));
         }
       }
-    if (a.out_amax) {
-      omax = wave_max_f(omax);
-      if (lane == 0) atomic_max_abs(a.out_amax, omax);
-    }
+    amax_flush(a.out_amax, omax, lane);
   } else if constexpr (EPI == E_QKV) {
     const int nqk = (a.Hq + a.Hk) * a.hd;
     const int px = a.hd == 64 ? 2 : 1;
@@ -683,8 +592,8 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
         for (int j = 0; j < 4; ++j) {
           const int n = nw + j * 16 + fr;
           if (n >= a.N) continue;
-          const float partner = n < nqk ? tot[i][j ^ px][e] * deq : 0.f;
-          emit_qkv_prec(a, P_BF16, m, n, tot[i][j][e] * deq, partner);
+          const float partner = n < nqk ? val(i, j ^ px, e) : 0.f;
+          emit_qkv_prec(a, P_BF16, m, n, val(i, j, e), partner);
         }
       }
   }
@@ -705,48 +614,18 @@ static void gemm_wide(const GemmArgs& a, hipStream_t s) {
 // w, w + nw, ...: for a part it issues the loads of the chunk's A fragments and the group's W
 // fragments together, runs every (row block, column block) MFMA chain from zero and leaves the
 // partial in LDS.  After one barrier the workgroup adds each output's partials in part order and
-// applies the epilogue.  A arrives normalised and quantised (norm_quant_kernel), so nothing but
-// loads precedes the MFMAs.  No cross-workgroup communication is needed.
+// applies the epilogue.  No cross-workgroup communication is needed.
 
 constexpr int SPLIT_WAVES = 16;
 constexpr int SPLIT_ROWS = 64;
 constexpr int SKINNY_ROWS = 256;  // below this many rows the split kernel is used
 
+// inv[a_rows[m]] = the RMSNorm scale of row a_rows[m] (for the output layer)
 __global__ void row_rms_kernel(const GemmArgs a, float* __restrict__ inv) {
-  const int m = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= a.M) return;
   const int ar = a.a_rows ? a.a_rows[m] : m;
-  const float v = row_inv_rms(static_cast<const float*>(a.A) + (long long)ar * a.K, a.K, a.eps,
-                              lane);
-  if (lane == 0) inv[ar] = v;
-}
-
-// y[m] = quantise(x[a_rows[m]] * inv * gain): the A operand of a normed GEMM, element for element
-// the value the fused prologues of the tile kernels produce.  One wave per row.
-template <int P>
-__global__ __launch_bounds__(256) void norm_quant_kernel(const GemmArgs a, void* __restrict__ y) {
-  constexpr int ES = PT<P>::ES;
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (m >= a.M) return;
-  const int K = a.K;
-  const int ar = a.a_rows ? a.a_rows[m] : m;
-  const float* xrow = static_cast<const float*>(a.A) + (long long)ar * K;
-  const float iv = a.inv ? a.inv[ar] : row_inv_rms(xrow, K, a.eps, lane);
-  const float a_inv = (P == P_FP8) ? 1.0f / a.a_scale : 1.0f;
-  uint8_t* yrow = static_cast<uint8_t*>(y) + (long long)m * K * ES;
-  float amax = 0.f;
-  for (int k = lane * 4; k < K; k += 256) {
-    float v[4];
-    norm4(xrow, a.gain, k, K, iv, v);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(v[i]));
-    PT<P>::put4(yrow + (long long)k * ES, v, a_inv);
-  }
-  if (a.a_amax) {
-    amax = wave_max_f(amax);
-    if (lane == 0) atomic_max_abs(a.a_amax, amax);
-  }
+  inv[ar] = inv_from_ssq(a.ssq + (long long)ar * (a.K / 16), a.K, a.eps);
 }
 
 __host__ __device__ __forceinline__ int group_size(int epi, int hd) {
@@ -767,10 +646,10 @@ __device__ __forceinline__ int group_block(int epi, int hd, int gi, int j) {
   return 2 * gi + j;
 }
 
-template <int P, int EPI, int MB>
+template <int P, int AM, int EPI, int MB>
 __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const GemmArgs a) {
   constexpr int ES = PT<P>::ES;
-  extern __shared__ float lds[];  // partials [part][block j][row block][16 rows][16 cols]
+  extern __shared__ float lds[];  // partials [part][block j][row block][16 rows][16 cols], inv[64]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
   const int K = a.K, N = a.N;
@@ -778,7 +657,8 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   const int gi = blockIdx.x, r0 = blockIdx.y * SPLIT_ROWS;
   const int M = min(a.M - r0, SPLIT_ROWS);
   const int gs = group_size(EPI, a.hd);
-  const uint8_t* A8 = static_cast<const uint8_t*>(a.A) + (long long)r0 * K * ES;
+  float* s_inv = lds + S * gs * MB * 256;
+  const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
   const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
   for (int s = wave; s < S; s += nw) {
     const int k0 = s * KP;
@@ -794,10 +674,12 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
       const int m = rb * 16 + fr;
-      if (m < M)
-        Frag<P>::load_raw(af[rb], A8 + (long long)m * K * ES, k0, K, fg);
-      else
+      if (m < M) {
+        const int ar = a.a_rows ? a.a_rows[r0 + m] : r0 + m;
+        Frag<P>::load_raw(af[rb], A8 + (long long)ar * K * ES, k0, K, fg);
+      } else {
         Frag<P>::zero(af[rb]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -812,13 +694,15 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       }
     }
   }
+  for (int m = threadIdx.x; m < M; m += blockDim.x)
+    s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
   __syncthreads();
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
-  // output (row m of the chunk, block j, column c) = partials summed in part order
+  // output (row m of the chunk, block j, column c) = (partials summed in part order) * deq * scale
   auto sum = [&](int m, int j, int c) {
     float v = 0.f;
     for (int s = 0; s < S; ++s) v += lds[(((s * gs + j) * MB + (m >> 4)) << 8) + (m & 15) * 16 + c];
-    return v * deq;
+    return v * deq * s_inv[m];
   };
   if constexpr (EPI == E_GLU) {
     float omax = 0.f;
@@ -828,10 +712,24 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       if (col < N / 2)
         omax = fmaxf(omax, emit_glu<P>(a, r0 + m, col, sum(m, 0, c), sum(m, 1, c)));
     }
-    if (a.out_amax) {
-      omax = wave_max_f(omax);
-      if (lane == 0) atomic_max_abs(a.out_amax, omax);
+    amax_flush(a.out_amax, omax, lane);
+  } else if constexpr (EPI == E_RESID) {
+    // one block per group; every lane takes part in the block sums of squares
+    float ymax = 0.f;
+    for (int t0 = 0; t0 < M * 16; t0 += blockDim.x) {
+      const int t = t0 + threadIdx.x;
+      const int m = t >> 4, c = t & 15;
+      const int n = gi * 16 + c;
+      const bool ok = t < M * 16 && n < N;
+      float xn = 0.f;
+      if (ok) {
+        float* o = a.out_f32 + (long long)(r0 + m) * a.ldo + n;
+        xn = *o + sum(m, 0, c);
+        *o = xn;
+      }
+      ymax = fmaxf(ymax, resid_out<P>(a, r0 + m, n, xn, c, ok));
     }
+    amax_flush(a.y_amax, ymax, lane);
   } else {
     const int nqk = (a.Hq + a.Hk) * a.hd;
     for (int t = threadIdx.x; t < M * gs * 16; t += blockDim.x) {
@@ -842,8 +740,6 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       const long long row = r0 + m;
       if constexpr (EPI == E_STORE) {
         a.out_f32[row * a.ldo + n] = v;
-      } else if constexpr (EPI == E_RESID) {
-        a.out_f32[row * a.ldo + n] += v;
       } else {
         float partner = 0.f;
         if (n < nqk) partner = a.hd == 16 ? sum(m, 0, c ^ 8) : sum(m, 1 - j, c);
@@ -1212,7 +1108,8 @@ __global__ __launch_bounds__(256) void attention_quad_kernel(const AttnArgs a) {
   state_put(a.ws + ((long long)item * MAXQ + qi) * QSTATE * 64, qs, lane);
 }
 
-// Few items, second kernel: quads -> groups -> output, one wave per item.
+// Few items, second kernel: quads -> groups -> output, one wave per item.  The (up to 4) quad
+// states of a group are loaded together before they are folded.
 template <int PO>
 __global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a) {
   const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
@@ -1222,14 +1119,17 @@ __global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a) {
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);
   const int qlo = c_lo / QCH, qhi = c_hi / QCH;
-  ChunkState run, gs, p;
+  const float* src = a.ws + (long long)item * MAXQ * QSTATE * 64;
+  ChunkState run, gs, p[GQ];
   state_empty(run);
   for (int g0 = (qlo / GQ) * GQ; g0 <= qhi; g0 += GQ) {
+#pragma unroll
+    for (int u = 0; u < GQ; ++u)
+      if (g0 + u >= qlo && g0 + u <= qhi) state_get(p[u], src + (g0 + u - qlo) * QSTATE * 64, lane);
     state_empty(gs);
-    for (int qq = max(g0, qlo); qq <= min(g0 + GQ - 1, qhi); ++qq) {
-      state_get(p, a.ws + ((long long)item * MAXQ + (qq - qlo)) * QSTATE * 64, lane);
-      fold(gs, p, nhb);
-    }
+#pragma unroll
+    for (int u = 0; u < GQ; ++u)
+      if (g0 + u >= qlo && g0 + u <= qhi) fold(gs, p[u], nhb);
     fold(run, gs, nhb);
   }
   float omax = attn_store<PO>(a, it, run, col, grp);
@@ -1242,15 +1142,32 @@ __global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a) {
 // ---- small kernels ------------------------------------------------------------------------
 
 // x[r] = E[tok]; one wave per row, which also writes the row's inverse RMS (row_inv_rms order).
+// x[r] = E[tok], the block sums of squares of the row, and y[r] = quantise(x[r] * gain)
+template <int P>
 __global__ void embed_kernel(const float* __restrict__ E, const RowMeta* __restrict__ rows, int n,
-                             int d, float* __restrict__ x, float* __restrict__ inv, float eps) {
+                             int d, float* __restrict__ x, float* __restrict__ ssq, void* y,
+                             const float* __restrict__ gain, float inv_scale, float* y_amax) {
   const int r = blockIdx.x;
   if (r >= n) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, c = lane & 15, q = lane >> 4;
+  const int nb = d / 16;
   const long long t = rows[r].tok;
-  for (int k = lane; k < d; k += 64) x[(long long)r * d + k] = E[t * d + k];
-  const float v = row_inv_rms(E + t * d, d, eps, lane);
-  if (inv && lane == 0) inv[r] = v;
+  float ymax = 0.f;
+  for (int b0 = 0; b0 < nb; b0 += 4) {
+    const int b = b0 + q;
+    const bool ok = b < nb;
+    const int k = 16 * b + c;
+    const float v = ok ? E[t * d + k] : 0.f;
+    const float sq = block_ssq16(v);
+    if (ok) {
+      x[(long long)r * d + k] = v;
+      if (c == 0) ssq[(long long)r * nb + b] = sq;
+      const float yv = v * gain[k];
+      PT<P>::store(y, (long long)r * d + k, yv, inv_scale);
+      ymax = fmaxf(ymax, fabsf(yv));
+    }
+  }
+  amax_flush(y_amax, ymax, lane);
 }
 
 template <int P>
@@ -1273,26 +1190,25 @@ static void gemm_go(const GemmArgs& a, hipStream_t s) {
 
 constexpr size_t kSplitLdsMax = 144 * 1024;  // of the 160 KiB LDS of a gfx950 CU
 
-template <int P, int EPI, int MB>
+template <int P, int AM, int EPI, int MB>
 static void launch_split(dim3 grid, dim3 block, size_t lds, const GemmArgs& a, hipStream_t s) {
   static bool raised = false;  // allow more than the default 64 KiB of dynamic LDS, once
   if (!raised) {
-    NC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_split_kernel<P, EPI, MB>),
+    NC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_split_kernel<P, AM, EPI, MB>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(kSplitLdsMax)));
     raised = true;
   }
-  hipLaunchKernelGGL((gemm_split_kernel<P, EPI, MB>), grid, block, lds, s, a);
+  hipLaunchKernelGGL((gemm_split_kernel<P, AM, EPI, MB>), grid, block, lds, s, a);
 }
 
 static int split_mb(int M) { return std::min((M + 15) / 16, SPLIT_ROWS / 16); }
 
 static size_t split_lds(const GemmArgs& a, int epi) {
   const int S = (a.K + KP - 1) / KP;
-  return size_t(S) * group_size(epi, a.hd) * split_mb(a.M) * 256 * sizeof(float);
+  return (size_t(S) * group_size(epi, a.hd) * split_mb(a.M) * 256 + SPLIT_ROWS) * sizeof(float);
 }
 
-// a.A is the quantised A operand ([M][K], precision P), a.a_rows unused
-template <int P, int EPI>
+template <int P, int AM, int EPI>
 static void gemm_split(const GemmArgs& a, hipStream_t s) {
   const int S = (a.K + KP - 1) / KP;
   const int nblk = (a.N + 15) / 16;
@@ -1303,36 +1219,22 @@ static void gemm_split(const GemmArgs& a, hipStream_t s) {
   const dim3 grid(ngroups, (a.M + SPLIT_ROWS - 1) / SPLIT_ROWS), block(64 * waves);
   const size_t lds = split_lds(a, EPI);
   switch (mb) {
-    case 1: launch_split<P, EPI, 1>(grid, block, lds, a, s); break;
-    case 2: launch_split<P, EPI, 2>(grid, block, lds, a, s); break;
-    case 3: launch_split<P, EPI, 3>(grid, block, lds, a, s); break;
-    default: launch_split<P, EPI, 4>(grid, block, lds, a, s); break;
+    case 1: launch_split<P, AM, EPI, 1>(grid, block, lds, a, s); break;
+    case 2: launch_split<P, AM, EPI, 2>(grid, block, lds, a, s); break;
+    case 3: launch_split<P, AM, EPI, 3>(grid, block, lds, a, s); break;
+    default: launch_split<P, AM, EPI, 4>(grid, block, lds, a, s); break;
   }
 }
 
 void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s) {
   if (a.M <= 0) return;
-  hipLaunchKernelGGL(row_rms_kernel, dim3((a.M + 3) / 4), dim3(256), 0, s, a, inv);
+  hipLaunchKernelGGL(row_rms_kernel, dim3((a.M + 255) / 256), dim3(256), 0, s, a, inv);
   NC_HIP(hipGetLastError());
 }
 
-size_t gemm_workspace_bytes(int rows, int K) { return size_t(rows) * K * sizeof(float); }
-
 template <int P, int AM, int EPI>
 static void gemm_shape(const GemmArgs& a, hipStream_t s) {
-  if (a.M < SKINNY_ROWS && split_lds(a, EPI) <= kSplitLdsMax) {
-    GemmArgs b = a;
-    if constexpr (AM == A_NORM) {
-      NC_CHECK(a.a_ws && a.a_ws_bytes >= size_t(a.M) * a.K * PT<P>::ES, NC_E_INVALID,
-               "GEMM workspace too small");
-      hipLaunchKernelGGL(norm_quant_kernel<P>, dim3((a.M + 3) / 4), dim3(256), 0, s, a, a.a_ws);
-      b.A = a.a_ws;
-    } else {
-      NC_CHECK(a.a_rows == nullptr, NC_E_INVALID, "row gather needs a normed GEMM");
-    }
-    b.a_rows = nullptr;
-    return gemm_split<P, EPI>(b, s);
-  }
+  if (a.M < SKINNY_ROWS && split_lds(a, EPI) <= kSplitLdsMax) return gemm_split<P, AM, EPI>(a, s);
   if constexpr (P != P_F32) {
     if (a.M >= SKINNY_ROWS && (EPI != E_QKV || a.hd == 32 || a.hd == 64))
       return gemm_wide<P, AM, EPI>(a, s);
@@ -1370,6 +1272,9 @@ void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s)
   NC_CHECK(a.K % 16 == 0, NC_E_INVALID, "GEMM K must be a multiple of 16");
   if (epi == E_QKV) NC_CHECK(64 % a.hd == 0, NC_E_INVALID, "head_dim must divide 64");
   if (epi == E_GLU) NC_CHECK(a.N % 32 == 0, NC_E_INVALID, "d_ffn must be a multiple of 16");
+  if (amode == A_NORM) NC_CHECK(a.ssq || a.inv, NC_E_INVALID, "normed GEMM needs row statistics");
+  if (epi == E_RESID)
+    NC_CHECK(a.N % 16 == 0 && (!a.y_out || a.y_gain), NC_E_INVALID, "bad residual epilogue");
   if (prec == P_F32)
     gemm_prec<P_F32>(amode, epi, a, s);
   else if (prec == P_BF16)
@@ -1425,10 +1330,20 @@ void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parall
   NC_HIP(hipGetLastError());
 }
 
-void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, float* inv,
-                  float eps, hipStream_t s) {
+void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, float* ssq,
+                  void* y, const float* gain, int prec, float inv_scale, float* y_amax,
+                  hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(embed_kernel, dim3(n), dim3(64), 0, s, E, rows, n, d, x, inv, eps);
+  NC_CHECK(d % 16 == 0, NC_E_INVALID, "d_model must be a multiple of 16");
+  if (prec == P_F32)
+    hipLaunchKernelGGL(embed_kernel<P_F32>, dim3(n), dim3(64), 0, s, E, rows, n, d, x, ssq, y,
+                       gain, inv_scale, y_amax);
+  else if (prec == P_BF16)
+    hipLaunchKernelGGL(embed_kernel<P_BF16>, dim3(n), dim3(64), 0, s, E, rows, n, d, x, ssq, y,
+                       gain, inv_scale, y_amax);
+  else
+    hipLaunchKernelGGL(embed_kernel<P_FP8>, dim3(n), dim3(64), 0, s, E, rows, n, d, x, ssq, y,
+                       gain, inv_scale, y_amax);
   NC_HIP(hipGetLastError());
 }
 

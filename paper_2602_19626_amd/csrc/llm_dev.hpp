@@ -6,7 +6,10 @@
 namespace nc {
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
-enum AMode { A_NORM = 0, A_DIRECT = 1 };                    // fused RMSNorm prologue, or not
+// A_NORM: A holds quantise(x * gain) of residual rows x, and each output row is scaled by the
+// row's RMSNorm scale 1 / sqrt(mean(x^2) + eps) (RMSNorm(x) * gain * W^T, the scale applied after
+// the sum); A_DIRECT: plain A.
+enum AMode { A_NORM = 0, A_DIRECT = 1 };
 enum Epi { E_STORE = 0, E_RESID = 1, E_GLU = 2, E_QKV = 3 };  // epilogues
 
 // Per-row metadata of a transformer pass: which stream, which position, which token.
@@ -20,12 +23,13 @@ struct RowMeta {
 // Arguments of one GEMM C[M][N] = A[M][K] W[N][K]^T (+ epilogue).
 struct GemmArgs {
   int M, N, K;
-  const void* A;          // A_NORM: float x rows (ld = K); A_DIRECT: Prec rows (ld = K)
+  const void* A;          // Prec rows [rows][K]
   const int32_t* a_rows;  // optional gather: A row of output row m is a_rows[m]
-  const float* gain;      // A_NORM: RMSNorm gain [K]
+  // A_NORM row scales: inv[a_rows[m]] if given, else from the block sums of squares ssq[a_rows[m]]
+  const float* inv;
+  const float* ssq;       // [rows][K/16]
   float eps;
-  float a_scale;          // FP8: dequantisation scale of A (A_DIRECT) / quantisation (A_NORM)
-  float* a_amax;          // optional: max |normed A| (calibration; integer atomic max)
+  float a_scale;          // FP8: dequantisation scale of A
   const void* W;          // Prec [N][K]
   float w_scale;          // FP8 weight scale
   // epilogue outputs
@@ -34,6 +38,12 @@ struct GemmArgs {
   void* out_p;            // E_GLU: Prec h [M][N/2] (quantised with out_scale for FP8)
   float out_scale;        // FP8 activation scale of the produced tensor (1/scale applied)
   float* out_amax;        // optional: max |output| before quantisation (calibration)
+  // E_RESID: the updated rows also give the next normed GEMM its operand and row statistics
+  float* ssq_out;         // block sums of squares [M][N/16]
+  void* y_out;            // Prec quantise(x * y_gain) [M][N] (FP8: times y_inv_scale), or null
+  const float* y_gain;
+  float y_inv_scale;
+  float* y_amax;          // optional: max |x * y_gain| (calibration)
   // E_QKV
   const RowMeta* rows;
   const float* rope;      // [max_pos][hd/2][2] (cos, sin), built in float64, stored float32
@@ -42,9 +52,6 @@ struct GemmArgs {
   void* vt_cache;         // [stream][kvh][hd][R]
   long long kv_stride;    // elements per stream in k_cache / vt_cache (one layer)
   int Hq, Hk, hd, ring;
-  const float* inv;       // A_NORM: precomputed inverse RMS per A row (indexed like A), or null
-  void* a_ws;             // A_NORM with few rows: the quantised A operand is staged here
-  size_t a_ws_bytes;      // at least gemm_workspace_bytes(M, K)
 };
 
 // Attention work item: a block of up to 16 (query, head) columns of one stream and kv head.
@@ -77,14 +84,16 @@ struct AttnArgs {
 };
 
 void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s);
-// inverse RMS (row_inv_rms) of rows a.A[a_rows[m]] into inv[a_rows[m]]
+// RMSNorm scale of rows a_rows[m] (from a.ssq) into inv[a_rows[m]]
 void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s);
-size_t gemm_workspace_bytes(int rows, int K);
 void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parallel,
                       hipStream_t s);
 size_t attention_ws_bytes(int n_items);
-void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, float* inv,
-                  float eps, hipStream_t s);
+// x[r] = E[rows[r].tok], its block sums of squares ssq[r][d/16] and the first normed GEMM's
+// operand y[r] = quantise(x[r] * gain) in precision prec (FP8: times inv_scale)
+void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, float* ssq,
+                  void* y, const float* gain, int prec, float inv_scale, float* y_amax,
+                  hipStream_t s);
 void launch_convert(const float* src, void* dst, long long n, int prec, float inv_scale,
                     hipStream_t s);
 

@@ -90,8 +90,9 @@ struct nc_ctx {
   DevBuf<int32_t> lastrow;  // per stream: row of its last position in the latest pass
   DevBuf<float> xinv;       // inverse RMS of each pass row's residual
   DevBuf<float> aws;        // attention group states (decode path)
-  DevBuf<float> gws;        // quantised A operand of normed GEMMs with few rows
-  DevBuf<float> hinv;       // inverse RMS of each stream's newest residual (hlast)
+  DevBuf<float> xss;        // block sums of squares of each pass row's residual [rows][d/16]
+  DevBuf<float> hinv;       // RMSNorm scale of each stream's newest row (its operand in hlast)
+  DevBuf<float> yb;         // operand of the next normed GEMM, quantise(x * gain) [rows][d]
   DevBuf<uint8_t> dstage;   // per-step staged inputs
   void* spin = nullptr;     // pinned host side of the stage
   size_t spin_bytes = 0;
@@ -128,7 +129,7 @@ nc_ctx::~nc_ctx() {
   if (dev >= 0) (void)hipSetDevice(dev);
   if (st) (void)hipStreamSynchronize(st);
   for (void* p : allocs) (void)hipFree(p);
-  DevBuf<float>* fb[] = {&gws, &aws, &xinv, &hinv, &amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
+  DevBuf<float>* fb[] = {&yb, &xss, &aws, &xinv, &hinv, &amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
                          &dbgp, &dbgpt};
   for (auto* q : fb) q->release();
   DevBuf<int32_t>* ib[] = {&uni, &nseen, &hist, &ncommit, &moded, &next_ctx, &keys, &kidx,
@@ -230,7 +231,7 @@ void prof_end(nc_ctx* c, int cls, double bytes, double flops) {
 double gemm_bytes(const GemmArgs& a, int amode, int epi, int prec, int att) {
   const double es = double(prec_bytes(prec));
   double b = double(a.N) * a.K * es;                                    // weights
-  b += double(a.M) * a.K * (amode == A_NORM ? 4.0 : es);                // activations
+  b += double(a.M) * a.K * es;                                          // activations
   if (epi == E_STORE) b += double(a.M) * a.N * 4.0;                     // logits
   if (epi == E_RESID) b += double(a.M) * a.N * 8.0;                     // residual read + write
   if (epi == E_GLU) b += double(a.M) * (a.N / 2) * es;                  // gated activation
@@ -308,6 +309,8 @@ void ensure_rows(nc_ctx* c, int rows) {
   const int r = std::max(rows, 64);
   c->x.alloc((size_t)r * c->d);
   c->xinv.alloc(r);
+  c->xss.alloc((size_t)r * (c->d / 16));
+  c->yb.alloc((size_t)r * c->d);  // sized for float32 (calibration pass)
   // sized for float32 so that the calibration pass (float32 GEMMs) fits in any precision
   c->qb.alloc((size_t)r * c->hq * c->hd * 4);
   c->ob.alloc((size_t)r * c->hq * c->hd * 4);
@@ -425,35 +428,20 @@ uint8_t* upload_stage(nc_ctx* c, const Stage& s) {
   return c->dstage.p;
 }
 
-__global__ void copy_rows_kernel(const float* x, const float* xinv, const int32_t* src_rows,
-                                 const int32_t* dst_rows, int n, int d, float* out, float* oinv) {
+// Newest rows of the streams: their output-layer operand rows (d elements of es bytes) and scales.
+__global__ void copy_rows_kernel(const uint32_t* y, const float* yinv, const int32_t* src_rows,
+                                 const int32_t* dst_rows, int n, int words, uint32_t* out,
+                                 float* oinv) {
   const int r = blockIdx.x;
   if (r >= n) return;
   const long long s = src_rows[r], t = dst_rows[r];
-  for (int k = threadIdx.x; k < d; k += blockDim.x) out[t * d + k] = x[s * d + k];
-  if (threadIdx.x == 0) oinv[t] = xinv[s];
+  for (int k = threadIdx.x; k < words; k += blockDim.x) out[t * words + k] = y[s * words + k];
+  if (threadIdx.x == 0) oinv[t] = yinv[s];
 }
 
-// Appends a planned pass to the KV caches; leaves each row's final residual in x and each
-// stream's newest row in hlast.  Rows of one stream are consecutive positions spanning fewer than
+// Appends a planned pass to the KV caches; leaves each row's final residual in x, its
+// output-layer operand in yb, and each stream's newest operand row in hlast.  Rows of one stream are consecutive positions spanning fewer than
 // `slide` positions (the ring holds ctx_len + slide entries, so no needed key is overwritten).
-// Workspace of a normed GEMM (its A operand, quantised, when it has few rows).
-static void gemm_ws(nc_ctx* c, GemmArgs& a) {
-  const size_t need = gemm_workspace_bytes(256, a.K);  // only GEMMs under 256 rows stage A
-  c->gws.alloc((need + 3) / 4);
-  a.a_ws = c->gws.p;
-  a.a_ws_bytes = c->gws.n * 4;
-}
-
-// Many-row bf16 / fp8 passes: the inverse RMS of every row once, ahead of a normed GEMM (the
-// wide tile kernel would otherwise recompute it in every column tile).  Same arithmetic as the
-// GEMMs' own computation.
-static void norm_rows(nc_ctx* c, GemmArgs& a, int n, int prec) {
-  if (n < 256 || prec == P_F32) return;
-  launch_row_rms(a, c->xinv.p, c->st);
-  a.inv = c->xinv.p;
-}
-
 void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = {}) {
   const int n = int(p.rows.size());
   if (!n) return;
@@ -464,7 +452,9 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
   (void)g;
   const int prec = o.calib ? P_F32 : c->prec;
   const int att = o.calib ? P_F32 : c->att;
-  launch_embed(c->E32, drows, n, c->d, c->x.p, c->xinv.p, c->cfg.norm_eps, c->st);
+  auto inv_scale = [&](float sc) { return prec == P_FP8 ? 1.0f / sc : 1.0f; };
+  launch_embed(c->E32, drows, n, c->d, c->x.p, c->xss.p, c->yb.p, c->layers[0].g_attn, prec,
+               inv_scale(c->layers[0].sa_qkv), o.calib ? c->amax.p : nullptr, c->st);
   const long long layer_kv = (long long)c->S_alloc * c->kv_stride * prec_bytes(c->att);
   for (int l = 0; l < c->nl; ++l) {
     Layer& L = c->layers[l];
@@ -474,11 +464,9 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     a.M = n;
     a.N = (c->hq + 2 * c->hk) * c->hd;
     a.K = c->d;
-    a.A = c->x.p;
-    a.gain = L.g_attn;
+    a.A = c->yb.p;
     a.eps = c->cfg.norm_eps;
     a.a_scale = L.sa_qkv;
-    a.a_amax = am ? am + 0 : nullptr;
     a.W = o.calib ? (void*)L.Wqkv32 : L.Wqkv;
     a.w_scale = o.calib ? 1.f : L.sw_qkv;
     a.rows = drows;
@@ -491,9 +479,8 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     a.Hk = c->hk;
     a.hd = c->hd;
     a.ring = c->R;
-    gemm_ws(c, a);
+    a.ssq = c->xss.p;
     prof_begin(c, NC_K_QKV);
-    norm_rows(c, a, n, prec);
     launch_gemm(prec, A_NORM, E_QKV, a, c->st);
     prof_end(c, NC_K_QKV, gemm_bytes(a, A_NORM, E_QKV, prec, att), 2.0 * a.M * a.N * a.K);
     // attention
@@ -534,6 +521,11 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     ob.w_scale = o.calib ? 1.f : L.sw_o;
     ob.out_f32 = c->x.p;
     ob.ldo = c->d;
+    ob.ssq_out = c->xss.p;
+    ob.y_out = c->yb.p;
+    ob.y_gain = L.g_mlp;
+    ob.y_inv_scale = inv_scale(L.sa_gu);
+    ob.y_amax = am ? am + 2 : nullptr;
     prof_begin(c, NC_K_OPROJ);
     launch_gemm(prec, A_DIRECT, E_RESID, ob, c->st);
     prof_end(c, NC_K_OPROJ, gemm_bytes(ob, A_DIRECT, E_RESID, prec, att), 2.0 * n * ob.N * ob.K);
@@ -542,19 +534,16 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     gu.M = n;
     gu.N = 2 * c->F;
     gu.K = c->d;
-    gu.A = c->x.p;
-    gu.gain = L.g_mlp;
+    gu.A = c->yb.p;
     gu.eps = c->cfg.norm_eps;
     gu.a_scale = L.sa_gu;
-    gu.a_amax = am ? am + 2 : nullptr;
     gu.W = o.calib ? (void*)L.Wgu32 : L.Wgu;
     gu.w_scale = o.calib ? 1.f : L.sw_gu;
     gu.out_p = c->hb.p;
     gu.out_scale = L.sa_d;
     gu.out_amax = am ? am + 3 : nullptr;
-    gemm_ws(c, gu);
+    gu.ssq = c->xss.p;
     prof_begin(c, NC_K_GATEUP);
-    norm_rows(c, gu, n, prec);
     launch_gemm(prec, A_NORM, E_GLU, gu, c->st);
     prof_end(c, NC_K_GATEUP, gemm_bytes(gu, A_NORM, E_GLU, prec, att), 2.0 * n * gu.N * gu.K);
     // down projection + residual
@@ -568,6 +557,13 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     dn.w_scale = o.calib ? 1.f : L.sw_d;
     dn.out_f32 = c->x.p;
     dn.ldo = c->d;
+    dn.ssq_out = c->xss.p;
+    // the next normed GEMM: the next layer's QKV, or the output layer
+    const bool last = l + 1 == c->nl;
+    dn.y_out = c->yb.p;
+    dn.y_gain = last ? c->g_final : c->layers[l + 1].g_attn;
+    dn.y_inv_scale = inv_scale(last ? c->sa_lm : c->layers[l + 1].sa_qkv);
+    dn.y_amax = o.calib ? c->amax.p + 4 * (l + 1) : nullptr;
     prof_begin(c, NC_K_DOWN);
     launch_gemm(prec, A_DIRECT, E_RESID, dn, c->st);
     prof_end(c, NC_K_DOWN, gemm_bytes(dn, A_DIRECT, E_RESID, prec, att), 2.0 * n * dn.N * dn.K);
@@ -575,22 +571,25 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
   const int nl = int(p.last.size() / 2);
   const int32_t* dl = reinterpret_cast<const int32_t*>(dstage + p.off_last);
   {
-    // inverse RMS of every final row, for the output layer (same arithmetic as the GEMMs)
+    // RMSNorm scale of every final row, for the output layer (same arithmetic as the GEMMs)
     GemmArgs r{};
     r.M = n;
     r.K = c->d;
-    r.A = c->x.p;
+    r.ssq = c->xss.p;
     r.eps = c->cfg.norm_eps;
     launch_row_rms(r, c->xinv.p, c->st);
   }
-  hipLaunchKernelGGL(copy_rows_kernel, dim3(nl), dim3(256), 0, c->st, c->x.p, c->xinv.p, dl,
-                     dl + nl, nl, c->d, c->hlast.p, c->hinv.p);
+  const int words = c->d * prec_bytes(prec) / 4;
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(nl), dim3(256), 0, c->st,
+                     reinterpret_cast<const uint32_t*>(c->yb.p), c->xinv.p, dl, dl + nl, nl, words,
+                     reinterpret_cast<uint32_t*>(c->hlast.p), c->hinv.p);
   NC_HIP(hipGetLastError());
   c->stats.body_rows += n;
 }
 
-// z[m] = final_norm(A[a_rows[m]]) E^T for m < M.
-void run_lm_head(nc_ctx* c, const float* A, const float* Ainv, const int32_t* a_rows, int M,
+// z[m] = final_norm(x) E^T for m < M, from the operand rows A[a_rows[m]] = quantise(x * g_final)
+// and their RMSNorm scales Ainv[a_rows[m]].
+void run_lm_head(nc_ctx* c, const void* A, const float* Ainv, const int32_t* a_rows, int M,
                  float* zout, bool calib = false) {
   GemmArgs a{};
   a.M = M;
@@ -598,16 +597,13 @@ void run_lm_head(nc_ctx* c, const float* A, const float* Ainv, const int32_t* a_
   a.K = c->d;
   a.A = A;
   a.a_rows = a_rows;
-  a.gain = c->g_final;
   a.eps = c->cfg.norm_eps;
   a.a_scale = c->sa_lm;
-  a.a_amax = calib ? c->amax.p + 4 * c->nl : nullptr;
   a.W = calib ? (void*)c->E32 : c->Elm;
   a.w_scale = calib ? 1.f : c->sw_lm;
   a.out_f32 = zout;
   a.ldo = c->V;
   a.inv = Ainv;
-  gemm_ws(c, a);
   const int prec = calib ? P_F32 : c->prec;
   prof_begin(c, NC_K_LMHEAD);
   launch_gemm(prec, A_NORM, E_STORE, a, c->st);
@@ -956,7 +952,7 @@ nc_status nc_calibrate_fp8(nc_ctx* c, const int32_t* tokens, size_t n) {
         run_pass(c, p, d, o);
         DevBuf<float> zt;
         zt.alloc(p.rows.size() * (size_t)c->V);
-        run_lm_head(c, c->x.p, c->xinv.p, reinterpret_cast<const int32_t*>(d + off_ar), int(p.rows.size()),
+        run_lm_head(c, c->yb.p, c->xinv.p, reinterpret_cast<const int32_t*>(d + off_ar), int(p.rows.size()),
                     zt.p, true);
         sync(c);
         zt.release();
@@ -1145,7 +1141,7 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
       const int32_t* seg_ar = reinterpret_cast<const int32_t*>(dst + off_ar);
       for (size_t i = 0; i < seg_len; ++i) {
         const int B = active[i];
-        run_lm_head(c, c->x.p, c->xinv.p, seg_ar + i * n, B, c->z.p);
+        run_lm_head(c, c->yb.p, c->xinv.p, seg_ar + i * n, B, c->z.p);
         StepArgs A = step_args(c, B, false);
         A.step_out = nullptr;
         A.iv = c->iv.p;
