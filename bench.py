@@ -38,6 +38,9 @@ KERNEL_SOURCES = {"qkv": "k_llm.hip", "attn": "k_llm.hip", "oproj": "k_llm.hip",
 KERNEL_NAME_RE = {"qkv": r"gemm_\w*kernel<\d+, \d+, 3\b", "gateup": r"gemm_\w*kernel<\d+, \d+, 2\b",
                   "lmhead": r"gemm_\w*kernel<\d+, \d+, 0\b", "attn": r"attention_\w*kernel",
                   "vocab": r"(vocab_\w*|ensemble_bias)_kernel", "ngram": r"ngram_\w*_kernel"}
+# one dispatch per class launch matches these (a class launch may run several kernels)
+KERNEL_PRIMARY_RE = {"attn": r"attention_(quad|seq)_kernel", "vocab": r"vocab_lse_kernel",
+                     "ngram": r"ngram_dense_kernel"}
 PROBE_RE = r"neg"   # the plain streaming probe kernel (torch.neg: reads N bytes, writes N bytes)
 
 
@@ -79,16 +82,42 @@ def traffic_from(fetch_csv: str, write_csv: str, kernel: str, workload: str, pro
     fscale, wscale = probe_bytes / pf[0], probe_bytes / pw[0]
     kf, kw = pick(f, KERNEL_NAME_RE[kernel]), pick(w, KERNEL_NAME_RE[kernel])
     assert kf and kw, f"no {kernel} dispatches in the counter files"
-    fb = sum(kf) / len(kf) * fscale
-    wb = sum(kw) / len(kw) * wscale
+    prim = KERNEL_PRIMARY_RE.get(kernel, KERNEL_NAME_RE[kernel])
+    launches = len(pick(f, prim))
+    assert launches > 0 and launches == len(pick(w, prim)), "counter runs disagree on launches"
+    fb = sum(kf) / launches * fscale
+    wb = sum(kw) / launches * wscale
     t = {"kernel": kernel, "workload": workload, "source_sha": kernel_source_hash(kernel),
-         "launches": len(kf), "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+         "launches": launches, "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
          "bytes_per_launch": round(fb + wb), "probe_bytes": probe_bytes,
          "fetch_scale": round(fscale, 5), "write_scale": round(wscale, 5), "command": command}
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     os.makedirs(os.path.dirname(path), exist_ok=True)
     json.dump(t, open(path, "w"), indent=1)
     return t
+
+
+def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024), reps: int = 20):
+    """nc_quantize_cdf24 alone (two kernels: segment reduce, segment scan) on float32 rows of
+    softmax-shaped probabilities; algorithmic bytes per row = read 4V + write 4(V + 1)."""
+    out = []
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for rows in rows_list:
+        z = torch.randn(rows, vocab, device="cuda", generator=g) * 3.0
+        p = torch.softmax(z, dim=1).contiguous()
+        nc.quantize_cdf24(p)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            nc.quantize_cdf24(p)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1000.0 / reps
+        gbs = rows * (8 * vocab + 4) / (us * 1e-6) / 1e9
+        out.append({"rows": rows, "vocab": vocab, "us_per_call": round(us, 2),
+                    "achieved_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
+    return out
 
 
 def cpu_baseline(wl, weights, stream, n_sample: int):
@@ -116,7 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="full_fp32")
-    ap.add_argument("--kernel", default="gateup", help="kernel class for the roofline")
+    ap.add_argument("--kernel", default="attn", help="kernel class for the roofline")
     ap.add_argument("--max-len", type=int, default=None, help="truncate streams (quick runs)")
     ap.add_argument("--n-streams", type=int, default=None)
     ap.add_argument("--cpu-sample", type=int, default=250)
@@ -228,6 +257,7 @@ def main():
             "skip_rate": None, "roundtrip_exact": bool(ok),
             "host_wait_frac": {"encode": round(w_enc / t_enc, 3), "decode": round(w_dec / t_dec, 3)},
             "roofline": roofline}
+    line["cdf24_standalone"] = cdf24_standalone(nc, torch, wl.shape.vocab)
     dstat = ctx.stats()
     line["skip_rate"] = round(dstat["skipped"] / max(dstat["tokens"], 1), 4)
     line["gpu_ideal_bits_per_token"] = round(st_enc["ideal_bits"] / n_tok, 5)

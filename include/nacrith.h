@@ -53,6 +53,7 @@ enum { NC_MODE_LLM = 0, NC_MODE_SKIP = 1, NC_MODE_MIX = 2, NC_MODE_ENSEMBLE = 3 
 
 /* Model shape, ensemble constants and run options.  All fields are read at nc_create(). */
 typedef struct nc_config {
+  /* d_model and d_ffn multiples of 16; head_dim 16, 32 or 64; vocab a multiple of 4 */
   int32_t n_layers, d_model, n_heads, n_kv_heads, head_dim, d_ffn, vocab;
   float rope_theta;          /* RoPE base; rotate-half pairs (i, i + head_dim/2) */
   float norm_eps;            /* RMSNorm epsilon */

@@ -6,7 +6,9 @@
 
 namespace nc {
 
-template <bool kVec4>
+// kLast: the final read of the row (streamed past the caches); the first pass keeps the row
+// cached, where the second pass finds it.
+template <bool kVec4, bool kLast>
 __device__ __forceinline__ void load_seg(const float* __restrict__ p, uint32_t seg, uint32_t V,
                                          float (&v)[4][4]) {
   const int tid = threadIdx.x;
@@ -14,7 +16,8 @@ __device__ __forceinline__ void load_seg(const float* __restrict__ p, uint32_t s
   for (int j = 0; j < 4; ++j) {
     const uint32_t idx = seg_index(seg, j, tid, 0);
     if (kVec4 && idx + 3 < V) {
-      const f4v q = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p + idx));
+      const f4v q = kLast ? __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p + idx))
+                          : *reinterpret_cast<const f4v*>(p + idx);
 #pragma unroll
       for (int i = 0; i < 4; ++i) v[j][i] = q[i];
     } else {
@@ -32,7 +35,7 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_reduce_kernel(
   __shared__ SegLds L;
   const uint32_t seg = blockIdx.x, row = blockIdx.y;
   float v[4][4];
-  load_seg<kVec4>(probs + size_t(row) * V, seg, V, v);
+  load_seg<kVec4, false>(probs + size_t(row) * V, seg, V, v);
   const SegPartial r = seg_reduce(v, seg, V, total - V, L);
   if (threadIdx.x == 0) parts[size_t(row) * nseg + seg] = r;
 }
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_scan_kernel(
   const int tid = threadIdx.x;
   if (tid < int(nseg)) L.parts[tid] = parts[size_t(row) * nseg + tid];
   float v[4][4];
-  load_seg<kVec4>(probs + size_t(row) * V, seg, V, v);
+  load_seg<kVec4, true>(probs + size_t(row) * V, seg, V, v);
   __syncthreads();
   const RowQuant q = seg_combine(L.parts, nseg, seg, V, total);
   uint32_t base[4];
@@ -72,6 +75,169 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_scan_kernel(
   }
 }
 
+// One workgroup per row for V <= 49,152 (768 threads; thread t owns entries 3072 q + 4 t .. + 3,
+// q < 16).  A first sweep reads the row, reduces the floor counts, the lowest-index argmax and
+// the validity, and keeps each lane's 4-entry count sums; one barrier round scans all sixteen
+// 3072-entry blocks at once (a wave scan per block, the wave totals exchanged through LDS); a
+// second sweep re-reads the row (now cached close by), recomputes the counts and stores each
+// lane's four CDF entries with the widest stores the row's alignment allows.  Every result is an
+// integer or a comparison, so it equals the two-kernel result.
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+constexpr int kRowThreads = 768;
+constexpr int kRowWaves = kRowThreads / 64;
+constexpr int kRowBlocks = 16;
+constexpr int kRowBlock = kRowThreads * 4;  // 3072 entries
+constexpr uint32_t kRowMaxV = kRowBlocks * kRowBlock;
+
+__device__ __forceinline__ void row_load4(const float* p, uint32_t i0, uint32_t V, float (&x)[4]) {
+  if (i0 + 3 < V) {
+    const f4v q = *reinterpret_cast<const f4v*>(p + i0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = q[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = i0 + i < V ? p[i0 + i] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __restrict__ probs,
+                                                                 uint32_t V, uint32_t total,
+                                                                 uint32_t* __restrict__ cdf,
+                                                                 int32_t* __restrict__ status) {
+  __shared__ uint64_t s_sum[kRowWaves];
+  __shared__ float s_best[kRowWaves];
+  __shared__ uint32_t s_bi[kRowWaves];
+  __shared__ int s_bad[kRowWaves];
+  __shared__ uint32_t s_wt[kRowWaves][kRowBlocks];
+  __shared__ uint32_t s_off[kRowWaves][kRowBlocks];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t row = blockIdx.x;
+  const float* p = probs + size_t(row) * V;
+  const uint32_t m = total - V;
+  // sweep 1
+  uint32_t s4[kRowBlocks];
+  uint64_t sum = 0;
+  float best = -1.f;
+  uint32_t bi = 0xFFFFFFFFu;
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < kRowBlocks; ++q) {
+    const uint32_t i0 = q * kRowBlock + 4 * tid;
+    float x[4];
+    row_load4(p, i0, V, x);
+    s4[q] = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i0 + i < V) {
+        if (!(x[i] >= 0.f && x[i] <= 1.f)) bad = 1;
+        s4[q] += floor_count(x[i], m);
+        if (x[i] > best) {
+          best = x[i];
+          bi = i0 + i;
+        }
+      }
+    sum += s4[q];
+  }
+  sum = wave_sum_u64(sum);
+  wave_argmax(best, bi);
+  bad = __any(bad) ? 1 : 0;
+  if (lane == 0) {
+    s_sum[w] = sum;
+    s_best[w] = best;
+    s_bi[w] = bi;
+    s_bad[w] = bad;
+  }
+  __syncthreads();
+  RowQuant rq;
+  {
+    uint64_t tot = 0;
+    float bv = -1.f;
+    uint32_t b = 0xFFFFFFFFu;
+    int bd = 0;
+    for (int k = 0; k < kRowWaves; ++k) {
+      tot += s_sum[k];
+      argmax_merge(bv, b, s_best[k], s_bi[k]);
+      bd |= s_bad[k];
+    }
+    const int64_t r = int64_t(total) - int64_t(tot);
+    rq.m = m;
+    rq.argmax = b;
+    rq.residual = int32_t(r);
+    rq.status = bd | (tot >= 0xFFFFFFFFull ? 1 : 0) | (b < V ? 0 : 1);
+    if (!rq.status && int64_t(floor_count(bv, m)) + r < 1) rq.status = 1;
+    rq.start = 0;
+  }
+  // the residual belongs to the argmax entry (corrected_count); per-block wave scans
+  uint32_t excl[kRowBlocks];
+#pragma unroll
+  for (int q = 0; q < kRowBlocks; ++q) {
+    const uint32_t i0 = q * kRowBlock + 4 * tid;
+    if (rq.argmax >= i0 && rq.argmax < i0 + 4) s4[q] = uint32_t(int32_t(s4[q]) + rq.residual);
+    uint32_t incl = s4[q];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) s_wt[w][q] = incl;
+    excl[q] = incl - s4[q];
+  }
+  __syncthreads();
+  // CDF value before wave k's part of block q: all earlier blocks, then earlier waves of block q
+  if (tid < kRowWaves * kRowBlocks) {
+    const int k = tid / kRowBlocks, q = tid % kRowBlocks;
+    uint32_t o = 0;
+    for (int qq = 0; qq < q; ++qq)
+      for (int kk = 0; kk < kRowWaves; ++kk) o += s_wt[kk][qq];
+    for (int kk = 0; kk < k; ++kk) o += s_wt[kk][q];
+    s_off[k][q] = o;
+  }
+  __syncthreads();
+  uint32_t* out = cdf + size_t(row) * (size_t(V) + 1);
+  if (tid == 0) {
+    out[0] = 0;
+    if (status) status[row] = rq.status;
+  }
+  // sweep 2: entries 3072 q + 4 t + i go to out[1 + 3072 q + 4 t + i]; every such group of four
+  // starts at the same word phase within the row
+  const uint32_t phase = uint32_t((reinterpret_cast<uintptr_t>(out + 1) >> 2) & 3);
+#pragma unroll
+  for (int q = 0; q < kRowBlocks; ++q) {
+    const uint32_t i0 = q * kRowBlock + 4 * tid;
+    if (i0 >= V) continue;
+    float x[4];
+    row_load4(p, i0, V, x);
+    uint32_t r4[4], run = s_off[w][q] + excl[q];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      run += i0 + i < V ? corrected_count(x[i], i0 + i, rq) : 0u;
+      r4[i] = run;
+    }
+    uint32_t* dst = out + 1 + i0;
+    if (i0 + 3 < V) {
+      if (phase == 0) {
+        __builtin_nontemporal_store(u4v{r4[0], r4[1], r4[2], r4[3]}, reinterpret_cast<u4v*>(dst));
+      } else if (phase == 2) {
+        __builtin_nontemporal_store(u2v{r4[0], r4[1]}, reinterpret_cast<u2v*>(dst));
+        __builtin_nontemporal_store(u2v{r4[2], r4[3]}, reinterpret_cast<u2v*>(dst + 2));
+      } else if (phase == 3) {
+        dst[0] = r4[0];
+        __builtin_nontemporal_store(u2v{r4[1], r4[2]}, reinterpret_cast<u2v*>(dst + 1));
+        dst[3] = r4[3];
+      } else {
+        dst[0] = r4[0];
+        dst[1] = r4[1];
+        __builtin_nontemporal_store(u2v{r4[2], r4[3]}, reinterpret_cast<u2v*>(dst + 2));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i0 + i < V) dst[i] = r4[i];
+    }
+  }
+}
+
 size_t quantize_workspace_bytes(uint32_t rows, uint32_t V) {
   return size_t(rows) * ceil_div(V, kSeg) * sizeof(SegPartial);
 }
@@ -79,8 +245,14 @@ size_t quantize_workspace_bytes(uint32_t rows, uint32_t V) {
 void launch_quantize_cdf(const float* p, uint32_t rows, uint32_t V, uint32_t total, uint32_t* cdf,
                          int32_t* status, void* workspace, hipStream_t s) {
   if (rows == 0) return;
-  const uint32_t nseg = uint32_t(ceil_div(V, kSeg));
   const bool vec = (V % 4 == 0) && (reinterpret_cast<uintptr_t>(p) % 16 == 0);
+  if (vec && V <= kRowMaxV) {
+    hipLaunchKernelGGL(cdf24_row_kernel, dim3(rows), dim3(kRowThreads), 0, s, p, V, total, cdf,
+                       status);
+    NC_HIP(hipGetLastError());
+    return;
+  }
+  const uint32_t nseg = uint32_t(ceil_div(V, kSeg));
   SegPartial* parts = static_cast<SegPartial*>(workspace);
   const dim3 grid(nseg, rows);
   if (vec) {

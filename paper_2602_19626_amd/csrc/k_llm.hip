@@ -182,6 +182,74 @@ __device__ __forceinline__ void emit_qkv_prec(const GemmArgs& a, int prec_att, i
     PT<P_BF16>::store(base, idx, v, 1.f);
 }
 
+// emit_qkv_prec for rows m .. m + 3 of one column (BF16 attention operands), element for element
+// the same arithmetic; V^T gets one 8-byte store when the rows are 4 consecutive ring slots of
+// one stream.
+__device__ __forceinline__ void emit_qkv4_bf16(const GemmArgs& a, int m, int n, const float (&v)[4],
+                                               const float (&partner)[4]) {
+  const int hd = a.hd, h2 = hd / 2;
+  const int nq = a.Hq * hd, nk = a.Hk * hd;
+  const int within = n % hd;
+  RowMeta rm[4];
+  bool ok[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    ok[e] = m + e < a.M;
+    rm[e] = ok[e] ? a.rows[m + e] : RowMeta{0, 0, 0, 0};
+  }
+  uint16_t h[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float x = v[e];
+    if (n < nq + nk) {
+      const int i = within < h2 ? within : within - h2;
+      const float cs = a.rope[((long long)rm[e].pos * h2 + i) * 2 + 0];
+      const float sn = a.rope[((long long)rm[e].pos * h2 + i) * 2 + 1];
+      x = within < h2 ? x * cs - partner[e] * sn : x * cs + partner[e] * sn;
+    }
+    h[e] = f2bf(x);
+  }
+  if (n < nq) {
+    uint16_t* Q = static_cast<uint16_t*>(a.q_out);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (ok[e]) Q[(long long)(m + e) * nq + n] = h[e];
+    return;
+  }
+  const int kv = n < nq + nk ? n - nq : n - nq - nk;
+  const int kvh = kv / hd;
+  if (n < nq + nk) {
+    uint16_t* Kc = static_cast<uint16_t*>(a.k_cache);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (ok[e]) {
+        const long long sb = (long long)rm[e].stream * a.kv_stride + (long long)kvh * a.ring * hd;
+        Kc[sb + (long long)(rm[e].pos % a.ring) * hd + within] = h[e];
+      }
+    return;
+  }
+  uint16_t* Vt = static_cast<uint16_t*>(a.vt_cache);
+  const int slot0 = rm[0].pos % a.ring;
+  bool run = ok[3] && (slot0 & 3) == 0 && slot0 + 3 < a.ring;
+#pragma unroll
+  for (int e = 1; e < 4; ++e)
+    run = run && rm[e].stream == rm[0].stream && rm[e].pos == rm[0].pos + e;
+  if (run) {
+    const long long sb = (long long)rm[0].stream * a.kv_stride + (long long)kvh * a.ring * hd;
+    uint2 w;
+    w.x = uint32_t(h[0]) | (uint32_t(h[1]) << 16);
+    w.y = uint32_t(h[2]) | (uint32_t(h[3]) << 16);
+    *reinterpret_cast<uint2*>(Vt + sb + (long long)within * a.ring + slot0) = w;
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (ok[e]) {
+      const long long sb = (long long)rm[e].stream * a.kv_stride + (long long)kvh * a.ring * hd;
+      Vt[sb + (long long)within * a.ring + rm[e].pos % a.ring] = h[e];
+    }
+}
+
 template <int P>
 __device__ __forceinline__ float emit_glu(const GemmArgs& a, int m, int col, float g, float u) {
   const float h = g / (1.0f + expf(-g)) * u;
@@ -583,19 +651,22 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
     const int nqk = (a.Hq + a.Hk) * a.hd;
     const int px = a.hd == 64 ? 2 : 1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      const int m = mw + i * 16 + fg * 4;
+      if (m >= a.M) continue;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int m = mw + i * 16 + fg * 4 + e;
-        if (m >= a.M) continue;
+      for (int j = 0; j < 4; ++j) {
+        const int n = nw + j * 16 + fr;
+        if (n >= a.N) continue;
+        float v[4], pr[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int n = nw + j * 16 + fr;
-          if (n >= a.N) continue;
-          const float partner = n < nqk ? val(i, j ^ px, e) : 0.f;
-          emit_qkv_prec(a, P_BF16, m, n, val(i, j, e), partner);
+        for (int e = 0; e < 4; ++e) {
+          v[e] = val(i, j, e);
+          pr[e] = n < nqk ? val(i, j ^ px, e) : 0.f;
         }
+        emit_qkv4_bf16(a, m, n, v, pr);
       }
+    }
   }
 }
 

@@ -50,17 +50,24 @@ __device__ __forceinline__ float head_logit(const RowIn& R, int t) {
   return R.use_head ? R.z[t] + R.b[t] : R.z[t];
 }
 
-// Coding probability of entry t; *pt receives the bias-head probability softmax(z + b)_t.
-__device__ __forceinline__ float row_prob(const RowIn& R, int t, float* pt) {
+// Coding probability of entry t from its logit z, bias b and n-gram probability g; *pt receives
+// the bias-head probability softmax(z + b)_t.
+__device__ __forceinline__ float row_prob_v(const RowIn& R, int t, float z, float b, float g,
+                                            float* pt) {
   float q = 0.f;
-  if (R.mode != M_SKIP) q = expf(head_logit(R, t) - R.lse);
+  if (R.mode != M_SKIP) q = expf((R.use_head ? z + b : z) - R.lse);
   *pt = q;
   if (R.mode == M_LLM) return q;
-  if (R.mode == M_SKIP) return R.png[t];
-  if (R.mode == M_MIX) return R.w[0] * q + R.w[1] * R.png[t];
+  if (R.mode == M_SKIP) return g;
+  if (R.mode == M_MIX) return R.w[0] * q + R.w[1] * g;
   float p = R.w[0] * q;
   for (int j = 1; j <= R.K; ++j) p = p + R.w[j] * R.pk[(size_t)(j - 1) * R.V + t];
   return p;
+}
+
+__device__ __forceinline__ float row_prob(const RowIn& R, int t, float* pt) {
+  return row_prob_v(R, t, R.mode != M_SKIP ? R.z[t] : 0.f, R.use_head && R.mode != M_SKIP ? R.b[t] : 0.f,
+                    R.mode != M_LLM ? R.png[t] : 0.f, pt);
 }
 
 // Mixture / gate weights of a stream: mixer w = exp(log w); ensemble w = softmax(theta).
@@ -96,13 +103,23 @@ __global__ __launch_bounds__(kSegThreads) void vocab_lse_kernel(VocabParams P, S
     float u[4][4];
     float m = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t0 = seg_index(seg, j, tid, 0);
+      if (t0 + 3 < uint32_t(V)) {
+        const f4v zz = *reinterpret_cast<const f4v*>(z + t0);
+        const f4v bb = P.use_head ? *reinterpret_cast<const f4v*>(b + t0) : f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t t = seg_index(seg, j, tid, i);
-        u[j][i] = t < uint32_t(V) ? (P.use_head ? z[t] + b[t] : z[t]) : -INFINITY;
-        m = fmaxf(m, u[j][i]);
+        for (int i = 0; i < 4; ++i) u[j][i] = P.use_head ? zz[i] + bb[i] : zz[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t t = t0 + i;
+          u[j][i] = t < uint32_t(V) ? (P.use_head ? z[t] + b[t] : z[t]) : -INFINITY;
+        }
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) m = fmaxf(m, u[j][i]);
+    }
     float sum = 0.f;
     if (m != -INFINITY)
 #pragma unroll
@@ -143,21 +160,35 @@ __device__ __forceinline__ RowIn make_row(const VocabParams& P, const StreamStat
   return R;
 }
 
+// Probabilities of this thread's 16 entries of segment seg (4 contiguous per quarter, loaded as
+// vectors), zero at or beyond V.
 __device__ __forceinline__ void row_probs(const RowIn& R, uint32_t seg, float (&p)[4][4],
                                           float (&pt)[4][4]) {
   const int tid = threadIdx.x;
+  const bool llm = R.mode != M_SKIP, ng = R.mode != M_LLM, hb = R.use_head && llm;
+  const f4v zero4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t t0 = seg_index(seg, j, tid, 0);
+    if (t0 + 3 < uint32_t(R.V)) {
+      const f4v zz = llm ? *reinterpret_cast<const f4v*>(R.z + t0) : zero4;
+      const f4v bb = hb ? *reinterpret_cast<const f4v*>(R.b + t0) : zero4;
+      const f4v gg = ng ? *reinterpret_cast<const f4v*>(R.png + t0) : zero4;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t t = seg_index(seg, j, tid, i);
-      if (t < uint32_t(R.V)) {
-        p[j][i] = row_prob(R, int(t), &pt[j][i]);
-      } else {
-        p[j][i] = 0.f;
-        pt[j][i] = 0.f;
+      for (int i = 0; i < 4; ++i) p[j][i] = row_prob_v(R, int(t0) + i, zz[i], bb[i], gg[i], &pt[j][i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t t = t0 + i;
+        if (t < uint32_t(R.V)) {
+          p[j][i] = row_prob(R, int(t), &pt[j][i]);
+        } else {
+          p[j][i] = 0.f;
+          pt[j][i] = 0.f;
+        }
       }
     }
+  }
 }
 
 // ---- V2: count partials --------------------------------------------------------------------

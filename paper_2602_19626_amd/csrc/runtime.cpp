@@ -791,7 +791,8 @@ void check_config(const nc_config* cfg) {
   NC_CHECK(cfg->head_dim >= 16 && cfg->head_dim <= 64 && 64 % cfg->head_dim == 0, NC_E_INVALID,
            "head_dim must be 16, 32 or 64");
   NC_CHECK(cfg->d_ffn > 0 && cfg->d_ffn % 16 == 0, NC_E_INVALID, "d_ffn must be a multiple of 16");
-  NC_CHECK(cfg->vocab >= 2 && cfg->vocab <= 262144, NC_E_INVALID, "vocab must be in [2, 262144]");
+  NC_CHECK(cfg->vocab >= 4 && cfg->vocab <= 262144 && cfg->vocab % 4 == 0, NC_E_INVALID,
+           "vocab must be a multiple of 4 in [4, 262144]");
   NC_CHECK(cfg->cdf_total > (uint32_t)cfg->vocab && cfg->cdf_total <= (1u << 24), NC_E_INVALID,
            "cdf_total must satisfy vocab < total <= 2^24");
   NC_CHECK(cfg->slide > 0 && cfg->ctx_len >= cfg->slide && cfg->ctx_len % cfg->slide == 0 &&

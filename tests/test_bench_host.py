@@ -39,3 +39,22 @@ def test_traffic_from_scales_by_probe(tmp_path, monkeypatch):
     assert bench.load_traffic("gateup", "full_fp32") == t["bytes_per_launch"]
     (tmp_path / "paper_2602_19626_amd" / "csrc" / "k_llm.hip").write_text("// changed")
     assert bench.load_traffic("gateup", "full_fp32") is None
+
+
+def test_traffic_from_counts_class_launches(tmp_path, monkeypatch):
+    """A class launch of several kernels (attention: quad + fold) is one launch."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "paper_2602_19626_amd" / "csrc")
+    (tmp_path / "paper_2602_19626_amd" / "csrc" / "k_llm.hip").write_text("// src")
+    probe = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda>"
+    quad, fold = "void nc::attention_quad_kernel<0>", "void nc::attention_fold_kernel<0>"
+    seq = "void nc::attention_seq_kernel<0, 0>"
+    rows_f = [(probe, 65536.0), (quad, 100.0), (fold, 10.0), (quad, 300.0), (fold, 30.0), (seq, 60.0)]
+    rows_w = [(probe, 65536.0), (quad, 1.0), (fold, 2.0), (quad, 1.0), (fold, 2.0), (seq, 3.0)]
+    _write(tmp_path / "f.csv", "FETCH_SIZE", rows_f)
+    _write(tmp_path / "w.csv", "WRITE_SIZE", rows_w)
+    t = bench.traffic_from(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "attn",
+                           "full_fp32", 64, "cmd")
+    assert t["launches"] == 3
+    assert t["fetch_bytes_per_launch"] == round(500 * 1024 / 3)
+    assert t["write_bytes_per_launch"] == round(9 * 1024 / 3)
