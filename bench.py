@@ -120,6 +120,54 @@ def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024), reps: int = 20
     return out
 
 
+# The paper's incremental feature ladder (ablation table), on synthetic streams.
+ABLATION = [
+    ("A0: LLM + coder, CDF-16", dict(cdf_total=1 << 16, use_head=False, use_ngram=False,
+                                     use_skip=False, use_mixer=False)),
+    ("A1: + CDF-24", dict(cdf_total=1 << 24, use_head=False, use_ngram=False, use_skip=False,
+                          use_mixer=False)),
+    ("A2: + adaptive head", dict(cdf_total=1 << 24, use_head=True, use_ngram=False,
+                                 use_skip=False, use_mixer=False)),
+    ("A3: + n-gram + skip", dict(cdf_total=1 << 24, use_head=True, use_ngram=True, use_skip=True,
+                                 use_mixer=False)),
+    ("A4: full system", dict(cdf_total=1 << 24, use_head=True, use_ngram=True, use_skip=True,
+                             use_mixer=True)),
+]
+
+
+def ablation(nc, wl, weights, streams, n_oracle: int):
+    """Each ladder step: GPU encode + decode of the streams (bits, rate, round trip) and, on a
+    prefix of the first stream, the FP64 oracle's coded bits for the same switches."""
+    import synth
+    from oracle import pipeline as op
+    rows = []
+    n_tok = int(sum(len(x) for x in streams))
+    for name, over in ABLATION:
+        cfg = nc.make_config(wl.shape, ngram_order=wl.ngram_order, precision=wl.precision,
+                             skip=wl.skip, mix_init=wl.mix_init, warmup=wl.warmup,
+                             head_lr=wl.head_lr, max_streams=len(streams), **over)
+        ctx = nc.Context(cfg, synth.flat_weights(wl.shape, weights))
+        t0 = time.perf_counter()
+        data, bits = ctx.encode_stream(streams)
+        out = ctx.decode_stream(data, [len(x) for x in streams])
+        dt = time.perf_counter() - t0
+        ok = all(np.array_equal(a, b) for a, b in zip(out, streams))
+        st = ctx.stats()
+        pre = streams[0][:n_oracle]
+        _, pb = ctx.encode_stream([pre])
+        ref = op.encode(op.Settings.from_workload(wl, **over), wl.shape, weights, pre)
+        bpt = float(sum(bits)) / n_tok
+        rows.append({"config": name, "bits_per_token": round(bpt, 5),
+                     "bpb_at_4_bytes_per_token": round(bpt / 4.0, 5),
+                     "tok_s_encode_decode": round(n_tok / dt, 1),
+                     "skip_rate": round(st["skipped"] / max(st["tokens"], 1), 4),
+                     "roundtrip_exact": bool(ok),
+                     "oracle_prefix_tokens": len(pre),
+                     "gpu_minus_oracle_bits_per_token_prefix":
+                         round((float(pb[0]) - float(ref.n_bits)) / len(pre), 5)})
+    return rows
+
+
 def cpu_baseline(wl, weights, stream, n_sample: int):
     """The oracle (FP64 numpy + exact integer quantiser + Python-integer coder) on a prefix."""
     from threadpoolctl import threadpool_info
@@ -155,6 +203,9 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="offline: turn two rocprofv3 --pmc counter files into the traffic figure")
     ap.add_argument("--traffic-command", default="", help="the counter runs' command, recorded")
+    ap.add_argument("--ablation", action="store_true",
+                    help="run the A0-A4 feature ladder on the workload instead of the timing")
+    ap.add_argument("--oracle-prefix", type=int, default=200)
     args = ap.parse_args()
     if args.traffic_from:
         print(json.dumps(traffic_from(*args.traffic_from, args.kernel, args.workload,
@@ -187,6 +238,11 @@ def main():
                          skip=wl.skip, mix_init=wl.mix_init, warmup=wl.warmup,
                          head_lr=wl.head_lr, cdf_total=wl.cdf_total, ensemble=wl.ensemble,
                          max_streams=len(streams))
+    if args.ablation:
+        print(json.dumps({"workload": args.workload, "streams": len(streams), "tokens": n_tok,
+                          "ablation": ablation(nc, wl, weights, streams, args.oracle_prefix)}),
+              flush=True)
+        return
     ctx = nc.Context(cfg, synth.flat_weights(wl.shape, weights))
     if wl.precision == "fp8":
         ctx.calibrate_fp8(synth.make_stream(2048, wl.shape.vocab, synth.CALIBRATION_SEED,

@@ -111,10 +111,11 @@ struct SegLds {
   uint32_t bcast[8];
 };
 
-// First pass: reduce one segment of probabilities p[j][i] (already zero at or beyond V).
+// First pass: reduce one segment of probabilities p[j][i] (already zero at or beyond V); tid is
+// the thread's index within its 256-thread segment group.
 __device__ __forceinline__ SegPartial seg_reduce(const float (&p)[4][4], uint32_t seg, uint32_t V,
-                                                 uint32_t m, SegLds& L) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+                                                 uint32_t m, SegLds& L, int tid) {
+  const int lane = tid & 63, w = tid >> 6;
   int bad = 0;
   uint64_t sum = 0;
   float best = -1.f;
@@ -189,8 +190,9 @@ __device__ __forceinline__ RowQuant seg_combine(const SegPartial* parts, uint32_
 // Second pass, segment part: exclusive scan of the corrected counts of this segment.  On return
 // base[j] = cdf[seg_index(seg, j, tid, 0)], so cdf[idx + 1] = base[j] + c'_{j,0} + ... + c'_{j,i}.
 __device__ __forceinline__ void seg_scan(const float (&p)[4][4], uint32_t seg, uint32_t V,
-                                         const RowQuant& q, uint32_t (&base)[4], SegLds& L) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+                                         const RowQuant& q, uint32_t (&base)[4], SegLds& L,
+                                         int tid) {
+  const int lane = tid & 63, w = tid >> 6;
   uint32_t excl[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_reduce_kernel(
   const uint32_t seg = blockIdx.x, row = blockIdx.y;
   float v[4][4];
   load_seg<kVec4, false>(probs + size_t(row) * V, seg, V, v);
-  const SegPartial r = seg_reduce(v, seg, V, total - V, L);
+  const SegPartial r = seg_reduce(v, seg, V, total - V, L, threadIdx.x);
   if (threadIdx.x == 0) parts[size_t(row) * nseg + seg] = r;
 }
 
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_scan_kernel(
   __syncthreads();
   const RowQuant q = seg_combine(L.parts, nseg, seg, V, total);
   uint32_t base[4];
-  seg_scan(v, seg, V, q, base, L);
+  seg_scan(v, seg, V, q, base, L, tid);
   uint32_t* out = cdf + size_t(row) * (size_t(V) + 1);
   if (seg == 0 && tid == 0) {
     out[0] = 0;

@@ -731,6 +731,9 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   float* s_inv = lds + S * gs * MB * 256;
   const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
   const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
+  // row scales first: their loads overlap the operand loads below
+  for (int m = threadIdx.x; m < M; m += blockDim.x)
+    s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
   for (int s = wave; s < S; s += nw) {
     const int k0 = s * KP;
     typename Frag<P>::T bf[2], af[MB];
@@ -765,8 +768,6 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       }
     }
   }
-  for (int m = threadIdx.x; m < M; m += blockDim.x)
-    s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
   __syncthreads();
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
   // output (row m of the chunk, block j, column c) = (partials summed in part order) * deq * scale
@@ -1022,8 +1023,17 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
   } else {
     const float* Kc = static_cast<const float*>(a.k_cache);
     const float* Vt = static_cast<const float*>(a.vt_cache);
-    // V^T fragments requested first so their latency overlaps the QK MFMAs
-    v4f vf[HDMAX / 16][4];
+    // every K and V^T fragment of the chunk requested before the first MFMA
+    v4f kf[4][4], vf[HDMAX / 16][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long long ks = sbase + (long long)((key0 + chunk_key(b, col)) % a.ring) * hd;
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd) {
+        const int k = 16 * grp + 4 * qd;
+        kf[b][qd] = k < hd ? *reinterpret_cast<const v4f*>(Kc + ks + k) : v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    }
 #pragma unroll
     for (int hb = 0; hb < HDMAX / 16; ++hb)
 #pragma unroll
@@ -1031,30 +1041,23 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
         vf[hb][b] = hb < nhb ? *reinterpret_cast<const v4f*>(
                                    Vt + sbase + (long long)(hb * 16 + col) * a.ring + vslot + 4 * b)
                              : v4f{0.f, 0.f, 0.f, 0.f};
+    // the four blocks' MFMA chains interleaved step by step
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const long long ks = sbase + (long long)((key0 + chunk_key(b, col)) % a.ring) * hd;
-      float kf[HDMAX / 4];
+    for (int b = 0; b < 4; ++b) st[b] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int qd = 0; qd < 4; ++qd) {
-        const int k = 16 * grp + 4 * qd;
-        const v4f v = k < hd ? *reinterpret_cast<const v4f*>(Kc + ks + k) : v4f{0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < HDMAX / 4; ++s)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) kf[4 * qd + e] = v[e];
-      }
-      st[b] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < HDMAX / 4; ++s)
-        st[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kf[s], q.f[s], st[b], 0, 0, 0);
-    }
+      for (int b = 0; b < 4; ++b)
+        st[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kf[b][s >> 2][s & 3], q.f[s], st[b], 0, 0, 0);
     chunk_softmax(st, a, c, key0, grp, r.m, r.l);
+    // the four hd blocks' P*V chains interleaved step by step (same order per chain)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int hb = 0; hb < HDMAX / 16; ++hb)
-        if (hb < nhb)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+        for (int hb = 0; hb < HDMAX / 16; ++hb)
+          if (hb < nhb)
             r.o[hb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[hb][b][j], st[b][j], r.o[hb], 0, 0, 0);
   }
   return r;

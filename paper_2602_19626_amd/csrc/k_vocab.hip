@@ -87,17 +87,22 @@ __device__ __forceinline__ void row_weights(const VocabParams& P, const float* l
 
 __device__ __forceinline__ bool uses_llm(int mode) { return mode != M_SKIP; }
 
-// ---- V1: logsumexp partials of z + b ---------------------------------------------------------
+// ---- the per-segment steps ------------------------------------------------------------------
+//
+// Each step is a device function of (segment, row, thread index within a 256-thread segment
+// group), run by one workgroup per (segment, row).  Steps that contain barriers take an `active`
+// flag: an inactive group passes through the barriers and touches nothing, so several groups of
+// one workgroup could share them.
 
-__global__ __launch_bounds__(kSegThreads) void vocab_lse_kernel(VocabParams P, StreamState S,
-                                                                StepArgs A) {
-  __shared__ LsePart wl[kSegWaves];
-  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
-  const int s = A.rows[r];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+// V1: logsumexp partial of z + b over one segment
+__device__ __forceinline__ void v1_seg(const VocabParams& P, const StreamState& S,
+                                       const StepArgs& A, int seg, int r, int nseg, int tid,
+                                       bool active, LsePart* wl) {
+  const int lane = tid & 63, w = tid >> 6;
   const int V = P.V;
+  const int s = A.rows[r];
   LsePart part{-INFINITY, 0.f};
-  if (uses_llm(S.mode[s])) {
+  if (active && uses_llm(S.mode[s])) {
     const float* z = A.z + (size_t)r * V;
     const float* b = S.b + (size_t)s * V;
     float u[4][4];
@@ -135,11 +140,12 @@ __global__ __launch_bounds__(kSegThreads) void vocab_lse_kernel(VocabParams P, S
   }
   if (lane == 0) wl[w] = part;
   __syncthreads();
-  if (tid == 0) {
+  if (active && tid == 0) {
     LsePart acc = wl[0];
     for (int k = 1; k < kSegWaves; ++k) acc = lse_merge(acc, wl[k]);
     A.lse_parts[(size_t)r * nseg + seg] = acc;
   }
+  __syncthreads();  // wl is reused by the next call
 }
 
 // Row setup shared by V2 and V3 (identical code, identical results).
@@ -162,9 +168,8 @@ __device__ __forceinline__ RowIn make_row(const VocabParams& P, const StreamStat
 
 // Probabilities of this thread's 16 entries of segment seg (4 contiguous per quarter, loaded as
 // vectors), zero at or beyond V.
-__device__ __forceinline__ void row_probs(const RowIn& R, uint32_t seg, float (&p)[4][4],
+__device__ __forceinline__ void row_probs(const RowIn& R, uint32_t seg, int tid, float (&p)[4][4],
                                           float (&pt)[4][4]) {
-  const int tid = threadIdx.x;
   const bool llm = R.mode != M_SKIP, ng = R.mode != M_LLM, hb = R.use_head && llm;
   const f4v zero4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -191,106 +196,122 @@ __device__ __forceinline__ void row_probs(const RowIn& R, uint32_t seg, float (&
   }
 }
 
-// ---- V2: count partials --------------------------------------------------------------------
-
-__global__ __launch_bounds__(kSegThreads) void vocab_count_kernel(VocabParams P, StreamState S,
-                                                                  StepArgs A) {
-  __shared__ SegLds L;
-  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
-  const int s = A.rows[r];
-  const RowIn R = make_row(P, S, A, r, s, nseg);
+// V2: count partial of one segment
+__device__ __forceinline__ void v2_seg(const VocabParams& P, const StreamState& S,
+                                       const StepArgs& A, int seg, int r, int nseg, int tid,
+                                       bool active, SegLds& L) {
   float p[4][4], pt[4][4];
-  row_probs(R, seg, p, pt);
-  const SegPartial sp = seg_reduce(p, seg, P.V, P.total - P.V, L);
-  if (threadIdx.x == 0) static_cast<SegPartial*>(A.seg_parts)[(size_t)r * nseg + seg] = sp;
+  RowIn R;
+  if (active) {
+    R = make_row(P, S, A, r, A.rows[r], nseg);
+    row_probs(R, seg, tid, p, pt);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p[j][i] = 0.f;
+  }
+  const SegPartial sp = seg_reduce(p, seg, P.V, P.total - P.V, L, tid);
+  if (active && tid == 0) static_cast<SegPartial*>(A.seg_parts)[(size_t)r * nseg + seg] = sp;
+  __syncthreads();  // L is reused by the next call
 }
 
-// ---- V3: scan, interval / search, bias-head update -----------------------------------------
-
-__global__ __launch_bounds__(kSegThreads) void vocab_scan_kernel(VocabParams P, StreamState S,
-                                                                 StepArgs A) {
-  __shared__ SegLds L;
-  __shared__ int s_sym;
-  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
-  const int tid = threadIdx.x;
-  const int s = A.rows[r];
+// V3: scan of one segment, the interval (encode) or the target search (decode), the outcome and
+// the bias-head step on the segment's entries
+__device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& S,
+                                       const StepArgs& A, int seg, int r, int nseg, int tid,
+                                       bool active, SegLds& L, int* s_sym) {
   const int V = P.V;
-  if (tid < nseg) L.parts[tid] = static_cast<const SegPartial*>(A.seg_parts)[(size_t)r * nseg + tid];
-  if (tid == 0) s_sym = -1;
-  const RowIn R = make_row(P, S, A, r, s, nseg);
+  const int s = A.rows[r];
+  if (active && tid < nseg)
+    L.parts[tid] = static_cast<const SegPartial*>(A.seg_parts)[(size_t)r * nseg + tid];
+  if (tid == 0) *s_sym = -1;
+  RowIn R;
   float p[4][4], pt[4][4];
-  row_probs(R, seg, p, pt);
+  if (active) {
+    R = make_row(P, S, A, r, s, nseg);
+    row_probs(R, seg, tid, p, pt);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p[j][i] = pt[j][i] = 0.f;
+  }
   __syncthreads();
-  const RowQuant q = seg_combine(L.parts, nseg, seg, V, P.total);
+  RowQuant q{};
+  if (active) q = seg_combine(L.parts, nseg, seg, V, P.total);
   uint32_t base[4];
-  seg_scan(p, seg, V, q, base, L);
-  const int i_pos = S.ncommit[s];
-  const uint32_t key = A.decode ? A.targets[r] : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]);
+  seg_scan(p, seg, V, q, base, L, tid);
+  const int i_pos = active ? S.ncommit[s] : 0;
+  const uint32_t key =
+      !active ? 0u : (A.decode ? A.targets[r] : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
   int found = -1;
   uint32_t fcl = 0, fch = 0;
   float fp = 0.f, fpt = 0.f;
+  if (active) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    uint32_t run = base[j];
+    for (int j = 0; j < 4; ++j) {
+      uint32_t run = base[j];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t t = seg_index(seg, j, tid, i);
-      if (t < uint32_t(V)) {
-        const uint32_t c = corrected_count(p[j][i], t, q);
-        const bool hit = A.decode ? (key >= run && key - run < c) : (t == key);
-        if (hit) {
-          found = int(t);
-          fcl = run;
-          fch = run + c;
-          fp = p[j][i];
-          fpt = pt[j][i];
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t t = seg_index(seg, j, tid, i);
+        if (t < uint32_t(V)) {
+          const uint32_t c = corrected_count(p[j][i], t, q);
+          const bool hit = A.decode ? (key >= run && key - run < c) : (t == key);
+          if (hit) {
+            found = int(t);
+            fcl = run;
+            fch = run + c;
+            fp = p[j][i];
+            fpt = pt[j][i];
+          }
+          if (A.dbg_cdf) A.dbg_cdf[(size_t)r * (V + 1) + t + 1] = run + c;
+          if (A.dbg_p) A.dbg_p[(size_t)r * V + t] = p[j][i];
+          if (A.dbg_pt) A.dbg_pt[(size_t)r * V + t] = pt[j][i];
+          run += c;
         }
-        if (A.dbg_cdf) A.dbg_cdf[(size_t)r * (V + 1) + t + 1] = run + c;
-        if (A.dbg_p) A.dbg_p[(size_t)r * V + t] = p[j][i];
-        if (A.dbg_pt) A.dbg_pt[(size_t)r * V + t] = pt[j][i];
-        run += c;
       }
     }
-  }
-  if (A.dbg_cdf && seg == 0 && tid == 0) A.dbg_cdf[(size_t)r * (V + 1)] = 0;
-  if (found >= 0 && !A.no_update) {
-    s_sym = found;
-    Outcome o;
-    o.sym = q.status ? -1 : found;
-    o.cl = fcl;
-    o.ch = fch;
-    o.mode = R.mode;
-    o.p = fp;
-    o.pt = fpt;
-    o.png = R.png[found];
-    o.lse = R.lse;
-    for (int k = 0; k < kMaxOrder; ++k)
-      o.pk[k] = (R.pk && k < P.K) ? R.pk[(size_t)k * V + found] : 0.f;
-    for (int k = 0; k < kMaxExperts; ++k) o.r[k] = 0.f;
-    if (R.mode == M_ENS) {
-      o.r[0] = R.w[0] * fpt / fp;
-      for (int k = 1; k <= P.K; ++k) o.r[k] = R.w[k] * o.pk[k - 1] / fp;
+    if (A.dbg_cdf && seg == 0 && tid == 0) A.dbg_cdf[(size_t)r * (V + 1)] = 0;
+    if (found >= 0 && !A.no_update) {
+      *s_sym = found;
+      Outcome o;
+      o.sym = q.status ? -1 : found;
+      o.cl = fcl;
+      o.ch = fch;
+      o.mode = R.mode;
+      o.p = fp;
+      o.pt = fpt;
+      o.png = R.png[found];
+      o.lse = R.lse;
+      for (int k = 0; k < kMaxOrder; ++k)
+        o.pk[k] = (R.pk && k < P.K) ? R.pk[(size_t)k * V + found] : 0.f;
+      for (int k = 0; k < kMaxExperts; ++k) o.r[k] = 0.f;
+      if (R.mode == M_ENS) {
+        o.r[0] = R.w[0] * fpt / fp;
+        for (int k = 1; k <= P.K; ++k) o.r[k] = R.w[k] * o.pk[k - 1] / fp;
+      }
+      A.out[r] = o;
+      if (A.iv) {
+        A.iv[((size_t)s * S.maxT + i_pos) * 2 + 0] = fcl;
+        A.iv[((size_t)s * S.maxT + i_pos) * 2 + 1] = fch;
+      }
+      if (A.ptok) A.ptok[(size_t)s * S.maxT + i_pos] = fp;
     }
-    A.out[r] = o;
-    if (A.iv) {
-      A.iv[((size_t)s * S.maxT + i_pos) * 2 + 0] = fcl;
-      A.iv[((size_t)s * S.maxT + i_pos) * 2 + 1] = fch;
+    if (found >= 0 && A.no_update) *s_sym = found;
+    if (q.status && seg == 0 && tid == 0) {
+      // invalid distribution: report through the outcome; no symbol can be coded
+      Outcome o{};
+      o.sym = -1;
+      o.mode = R.mode;
+      A.out[r] = o;
     }
-    if (A.ptok) A.ptok[(size_t)s * S.maxT + i_pos] = fp;
-  }
-  if (found >= 0 && A.no_update) s_sym = found;
-  if (q.status && seg == 0 && tid == 0) {
-    // invalid distribution: report through the outcome; no symbol can be coded
-    Outcome o{};
-    o.sym = -1;
-    o.mode = R.mode;
-    A.out[r] = o;
   }
   // bias-head SGD step on -log ptilde(t*), section 3.7 (entries of this segment only)
-  if (P.use_head && !P.ensemble && (R.mode == M_LLM || R.mode == M_MIX) && !q.status &&
+  __syncthreads();
+  if (active && P.use_head && !P.ensemble && (R.mode == M_LLM || R.mode == M_MIX) && !q.status &&
       !A.no_update) {
-    __syncthreads();
-    const int sym = A.decode ? s_sym : int(key);
+    const int sym = A.decode ? *s_sym : int(key);
     float* b = S.b + (size_t)s * V;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -303,13 +324,12 @@ __global__ __launch_bounds__(kSegThreads) void vocab_scan_kernel(VocabParams P, 
         }
       }
   }
+  __syncthreads();  // L and s_sym are reused by the next call
 }
 
-// ---- V4: ensemble backward + SGD on b ------------------------------------------------------
-
-__global__ __launch_bounds__(kSegThreads) void ensemble_bias_kernel(VocabParams P, StreamState S,
-                                                                    StepArgs A) {
-  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
+// V4: ensemble backward + SGD on b over one segment (no barriers)
+__device__ __forceinline__ void v4_seg(const VocabParams& P, const StreamState& S,
+                                       const StepArgs& A, int seg, int r, int tid) {
   const int s = A.rows[r];
   const Outcome o = A.out[r];
   if (o.sym < 0 || o.mode != M_ENS) return;
@@ -317,12 +337,11 @@ __global__ __launch_bounds__(kSegThreads) void ensemble_bias_kernel(VocabParams 
   const float* z = A.z + (size_t)r * V;
   float* b = S.b + (size_t)s * V;
   const float r0 = o.r[0];
-  (void)nseg;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const uint32_t t = seg_index(seg, j, threadIdx.x, i);
+      const uint32_t t = seg_index(seg, j, tid, i);
       if (t < uint32_t(V)) {
         const float q0 = expf(z[t] + b[t] - o.lse);
         const float ind = int(t) == o.sym ? 1.f : 0.f;
@@ -364,18 +383,18 @@ __device__ int ctx_find(const StreamState& S, size_t t, const int32_t* toks, int
   return -1;
 }
 
-__global__ __launch_bounds__(64) void ngram_update_kernel(VocabParams P, StreamState S,
-                                                          StepArgs A) {
-  const int r = blockIdx.x;
+// thread k of the row's update (k = 0: unigram, history, mixer / gate; k = 1..K: order-k table);
+// k < 0 does nothing but pass the barriers
+__device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& S,
+                                       const StepArgs& A, int r, int k) {
   const int s = A.rows[r];
   const Outcome o = A.out[r];
-  const int k = threadIdx.x;
-  if (o.sym < 0) return;
-  const int i = S.ncommit[s];
+  const bool on = k >= 0 && o.sym >= 0;
+  const int i = on ? S.ncommit[s] : 0;
   const int32_t* hist = S.hist + (size_t)s * S.maxT;
   const int sym = o.sym;
   __syncthreads();
-  if (k == 0) {
+  if (on && k == 0) {
     if (A.decode) S.hist[(size_t)s * S.maxT + i] = sym;
     if (P.use_ngram || P.ensemble) {
       S.uni[(size_t)s * P.V + sym] += 1;
@@ -396,7 +415,7 @@ __global__ __launch_bounds__(64) void ngram_update_kernel(VocabParams P, StreamS
       for (int j = 0; j <= P.K; ++j) lw[j] = lw[j] - P.head_lr * (w[j] - o.r[j]);
     }
   }
-  if ((P.use_ngram || P.ensemble) && k >= 1 && k <= P.K) {
+  if (on && (P.use_ngram || P.ensemble) && k >= 1 && k <= P.K) {
     const size_t t = (size_t)s * P.K + (k - 1);
     int32_t ctx[kMaxOrder];
     // insert t* as a continuation of the order-k context ending at t_{i-1}
@@ -449,7 +468,7 @@ __global__ __launch_bounds__(64) void ngram_update_kernel(VocabParams P, StreamS
     S.next_ctx[(size_t)s * kMaxOrder + (k - 1)] = nid;
   }
   __syncthreads();
-  if (k == 0) S.ncommit[s] = i + 1;
+  if (on && k == 0) S.ncommit[s] = i + 1;
 }
 
 // ---- V6: dense n-gram prediction of the current position ------------------------------------
@@ -483,37 +502,37 @@ __device__ __forceinline__ float ng_base(const StreamState& S, const NgRow& g, i
   return float(S.uni[(size_t)s * V + t] + 1) * g.inv_norm;
 }
 
-__global__ __launch_bounds__(kSegThreads) void ngram_dense_kernel(VocabParams P, StreamState S,
-                                                                  const int32_t* rows,
-                                                                  NgPart* parts) {
-  __shared__ NgPart wl[kSegWaves];
-  const int seg = blockIdx.x, r = blockIdx.y, nseg = gridDim.x;
-  const int s = rows[r];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+__device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& S,
+                                       const int32_t* rows, NgPart* parts, int seg, int r,
+                                       int nseg, int tid, bool active, NgPart* wl) {
+  const int lane = tid & 63, w = tid >> 6;
   const int V = P.V;
-  const NgRow g = ng_row(P, S, s);
+  const int s = rows[r];
   float h = 0.f, mx = 0.f;
+  if (active) {
+    const NgRow g = ng_row(P, S, s);
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t t = seg_index(seg, j, tid, i);
-      if (t < uint32_t(V)) {
-        float pv = ng_base(S, g, s, V, int(t));
-        for (int k = 1; k <= P.K; ++k) {
-          if (g.present[k - 1]) pv = (1.0f - g.lam[k - 1]) * pv;
-          if (S.pk) S.pk[((size_t)s * P.K + (k - 1)) * V + t] = pv;
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t t = seg_index(seg, j, tid, i);
+        if (t < uint32_t(V)) {
+          float pv = ng_base(S, g, s, V, int(t));
+          for (int k = 1; k <= P.K; ++k) {
+            if (g.present[k - 1]) pv = (1.0f - g.lam[k - 1]) * pv;
+            if (S.pk) S.pk[((size_t)s * P.K + (k - 1)) * V + t] = pv;
+          }
+          S.png[(size_t)s * V + t] = pv;
+          h = h - pv * log2f(pv);
+          mx = fmaxf(mx, pv);
         }
-        S.png[(size_t)s * V + t] = pv;
-        h = h - pv * log2f(pv);
-        mx = fmaxf(mx, pv);
       }
-    }
+  }
   h = wave_sum_f(h);
   mx = wave_max_f(mx);
   if (lane == 0) wl[w] = NgPart{h, mx};
   __syncthreads();
-  if (tid == 0) {
+  if (active && tid == 0) {
     NgPart acc = wl[0];
     for (int k = 1; k < kSegWaves; ++k) {
       acc.h += wl[k].h;
@@ -521,85 +540,94 @@ __global__ __launch_bounds__(kSegThreads) void ngram_dense_kernel(VocabParams P,
     }
     parts[(size_t)r * nseg + seg] = acc;
   }
+  __syncthreads();  // wl is reused by the next call
 }
 
 // ---- V7: sparse n-gram entries, entropy, skip decision ---------------------------------------
 
-__global__ __launch_bounds__(256) void ngram_fix_kernel(VocabParams P, StreamState S,
-                                                        const int32_t* rows, const NgPart* parts,
-                                                        int nseg, StepOut* step_out,
-                                                        const Outcome* out) {
-  __shared__ int lt[kMaxOrder][kSlots], lc[kMaxOrder][kSlots], ln[kMaxOrder];
-  __shared__ float sh[256], smx[256];
-  const int r = blockIdx.x;
-  const int s = rows[r];
-  const int tid = threadIdx.x;
+struct FixLds {
+  int lt[kMaxOrder][kSlots], lc[kMaxOrder][kSlots], ln[kMaxOrder];
+  float sh[kSegThreads], smx[kSegThreads];
+};
+
+// 256 threads (tid) of one row; active == false only passes the barriers
+__device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& S,
+                                       const int32_t* rows, const NgPart* parts, int nseg,
+                                       StepOut* step_out, const Outcome* out, int r, int tid,
+                                       bool active, FixLds& F) {
+  const int nt = kSegThreads;
   const int V = P.V;
-  const NgRow g = ng_row(P, S, s);
-  if (tid < kMaxOrder) ln[tid] = 0;
+  const int s = rows[r];
+  NgRow g{};
+  if (active) g = ng_row(P, S, s);
+  if (active && tid < kMaxOrder) F.ln[tid] = 0;
   __syncthreads();
-  for (int e = tid; e < P.K * kSlots; e += blockDim.x) {
-    const int k = e / kSlots + 1, j = e % kSlots;
-    if (!g.present[k - 1]) continue;
-    const int id = S.next_ctx[(size_t)s * kMaxOrder + (k - 1)];
-    const size_t t = (size_t)s * P.K + (k - 1);
-    const int n = S.pool_n[t * S.maxctx + id];
-    if (j == 0) ln[k - 1] = n;
-    if (j < n) {
-      lt[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 0];
-      lc[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 1];
+  if (active)
+    for (int e = tid; e < P.K * kSlots; e += nt) {
+      const int k = e / kSlots + 1, j = e % kSlots;
+      if (!g.present[k - 1]) continue;
+      const int id = S.next_ctx[(size_t)s * kMaxOrder + (k - 1)];
+      const size_t t = (size_t)s * P.K + (k - 1);
+      const int n = S.pool_n[t * S.maxctx + id];
+      if (j == 0) F.ln[k - 1] = n;
+      if (j < n) {
+        F.lt[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 0];
+        F.lc[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 1];
+      }
     }
-  }
   __syncthreads();
   float dh = 0.f, dmx = 0.f;
-  for (int e = tid; e < P.K * kSlots; e += blockDim.x) {
-    const int k = e / kSlots + 1, j = e % kSlots;
-    if (j >= ln[k - 1]) continue;
-    const int tok = lt[k - 1][j];
-    bool owner = true;  // first occurrence over (order, slot) in increasing order
-    for (int k2 = 1; k2 < k && owner; ++k2)
-      for (int j2 = 0; j2 < ln[k2 - 1]; ++j2)
-        if (lt[k2 - 1][j2] == tok) {
-          owner = false;
-          break;
+  if (active)
+    for (int e = tid; e < P.K * kSlots; e += nt) {
+      const int k = e / kSlots + 1, j = e % kSlots;
+      if (j >= F.ln[k - 1]) continue;
+      const int tok = F.lt[k - 1][j];
+      bool owner = true;  // first occurrence over (order, slot) in increasing order
+      for (int k2 = 1; k2 < k && owner; ++k2)
+        for (int j2 = 0; j2 < F.ln[k2 - 1]; ++j2)
+          if (F.lt[k2 - 1][j2] == tok) {
+            owner = false;
+            break;
+          }
+      if (!owner) continue;
+      // P_k(tok) = lambda_k Phat_k(tok) + (1 - lambda_k) P_{k-1}(tok), k = 1..K (section 3.5)
+      float pv = ng_base(S, g, s, V, tok);
+      for (int k2 = 1; k2 <= P.K; ++k2) {
+        if (g.present[k2 - 1]) {
+          int cnt = 0;
+          for (int j2 = 0; j2 < F.ln[k2 - 1]; ++j2)
+            if (F.lt[k2 - 1][j2] == tok) cnt = F.lc[k2 - 1][j2];
+          const int id = S.next_ctx[(size_t)s * kMaxOrder + (k2 - 1)];
+          const float n = float(S.pool_sum[((size_t)s * P.K + (k2 - 1)) * S.maxctx + id]);
+          pv = g.lam[k2 - 1] * (float(cnt) / n) + (1.0f - g.lam[k2 - 1]) * pv;
         }
-    if (!owner) continue;
-    // P_k(tok) = lambda_k Phat_k(tok) + (1 - lambda_k) P_{k-1}(tok), k = 1..K (section 3.5)
-    float pv = ng_base(S, g, s, V, tok);
-    for (int k2 = 1; k2 <= P.K; ++k2) {
-      if (g.present[k2 - 1]) {
-        int cnt = 0;
-        for (int j2 = 0; j2 < ln[k2 - 1]; ++j2)
-          if (lt[k2 - 1][j2] == tok) cnt = lc[k2 - 1][j2];
-        const int id = S.next_ctx[(size_t)s * kMaxOrder + (k2 - 1)];
-        const float n = float(S.pool_sum[((size_t)s * P.K + (k2 - 1)) * S.maxctx + id]);
-        pv = g.lam[k2 - 1] * (float(cnt) / n) + (1.0f - g.lam[k2 - 1]) * pv;
+        if (S.pk) S.pk[((size_t)s * P.K + (k2 - 1)) * V + tok] = pv;
       }
-      if (S.pk) S.pk[((size_t)s * P.K + (k2 - 1)) * V + tok] = pv;
+      const float old = S.png[(size_t)s * V + tok];
+      S.png[(size_t)s * V + tok] = pv;
+      dh = dh + (old * log2f(old) - pv * log2f(pv));
+      dmx = fmaxf(dmx, pv);
     }
-    const float old = S.png[(size_t)s * V + tok];
-    S.png[(size_t)s * V + tok] = pv;
-    dh = dh + (old * log2f(old) - pv * log2f(pv));
-    dmx = fmaxf(dmx, pv);
+  if (active) {
+    F.sh[tid] = dh;
+    F.smx[tid] = dmx;
   }
-  sh[tid] = dh;
-  smx[tid] = dmx;
   __syncthreads();
-  for (int d = blockDim.x / 2; d > 0; d >>= 1) {
-    if (tid < d) {
-      sh[tid] = sh[tid] + sh[tid + d];
-      smx[tid] = fmaxf(smx[tid], smx[tid + d]);
+  for (int d = nt / 2; d > 0; d >>= 1) {
+    if (active && tid < d) {
+      F.sh[tid] = F.sh[tid] + F.sh[tid + d];
+      F.smx[tid] = fmaxf(F.smx[tid], F.smx[tid + d]);
     }
     __syncthreads();
   }
-  if (tid == 0) {
+  if (active && tid == 0) {
     float H = 0.f, mx = 0.f;
     for (int k = 0; k < nseg; ++k) {
       H += parts[(size_t)r * nseg + k].h;
       mx = fmaxf(mx, parts[(size_t)r * nseg + k].mx);
     }
-    H = H + sh[0];
-    mx = fmaxf(mx, smx[0]);
+    H = H + F.sh[0];
+    mx = fmaxf(mx, F.smx[0]);
     S.H[s] = H;
     S.pmax[s] = mx;
     const int pos = S.ncommit[s];
@@ -627,6 +655,53 @@ __global__ __launch_bounds__(256) void ngram_fix_kernel(VocabParams P, StreamSta
       step_out[r] = so;
     }
   }
+}
+
+// ---- the segmented kernels: one workgroup per (segment, row) ---------------------------------
+
+__global__ __launch_bounds__(kSegThreads) void vocab_lse_kernel(VocabParams P, StreamState S,
+                                                                StepArgs A) {
+  __shared__ LsePart wl[kSegWaves];
+  v1_seg(P, S, A, blockIdx.x, blockIdx.y, gridDim.x, threadIdx.x, true, wl);
+}
+
+__global__ __launch_bounds__(kSegThreads) void vocab_count_kernel(VocabParams P, StreamState S,
+                                                                  StepArgs A) {
+  __shared__ SegLds L;
+  v2_seg(P, S, A, blockIdx.x, blockIdx.y, gridDim.x, threadIdx.x, true, L);
+}
+
+__global__ __launch_bounds__(kSegThreads) void vocab_scan_kernel(VocabParams P, StreamState S,
+                                                                 StepArgs A) {
+  __shared__ SegLds L;
+  __shared__ int s_sym;
+  v3_seg(P, S, A, blockIdx.x, blockIdx.y, gridDim.x, threadIdx.x, true, L, &s_sym);
+}
+
+__global__ __launch_bounds__(kSegThreads) void ensemble_bias_kernel(VocabParams P, StreamState S,
+                                                                    StepArgs A) {
+  v4_seg(P, S, A, blockIdx.x, blockIdx.y, threadIdx.x);
+}
+
+__global__ __launch_bounds__(64) void ngram_update_kernel(VocabParams P, StreamState S,
+                                                          StepArgs A) {
+  v5_row(P, S, A, blockIdx.x, threadIdx.x);
+}
+
+__global__ __launch_bounds__(kSegThreads) void ngram_dense_kernel(VocabParams P, StreamState S,
+                                                                  const int32_t* rows,
+                                                                  NgPart* parts) {
+  __shared__ NgPart wl[kSegWaves];
+  v6_seg(P, S, rows, parts, blockIdx.x, blockIdx.y, gridDim.x, threadIdx.x, true, wl);
+}
+
+__global__ __launch_bounds__(kSegThreads) void ngram_fix_kernel(VocabParams P, StreamState S,
+                                                                const int32_t* rows,
+                                                                const NgPart* parts, int nseg,
+                                                                StepOut* step_out,
+                                                                const Outcome* out) {
+  __shared__ FixLds F;
+  v7_row(P, S, rows, parts, nseg, step_out, out, blockIdx.x, threadIdx.x, true, F);
 }
 
 // ---- reset -----------------------------------------------------------------------------------

@@ -99,6 +99,7 @@ struct StepArgs {
   uint32_t* dbg_cdf;
 };
 
+// V1-V3, V4 for the ensemble and the V5 n-gram / mixer update (unless A.no_update)
 void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArgs& A,
                        hipStream_t s);
 // n-gram distribution, entropy and mode of the current position of each row's stream; with

@@ -104,3 +104,38 @@ def test_error_paths(setup):
     with pytest.raises(nc.NacrithError) as e:
         ctx.decode_stream([data[0][:3]], [200])       # truncated stream: decoder overrun
     assert e.value.status in (5,)
+
+
+def test_wide_batch_matches_streams_alone(setup):
+    """40 streams coded together give each stream the bytes it gets when coded alone."""
+    ctx, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    n = 40
+    streams = [synth.make_stream(96 + 3 * i, WL.shape.vocab, seed=300 + i, span=WL.span)
+               for i in range(n)]
+    alone = [ctx.encode_stream([s])[0][0] for s in streams[:6]]
+    cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32", skip=WL.skip,
+                         mix_init=WL.mix_init, max_streams=n)
+    big = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+    together, _ = big.encode_stream(streams)
+    assert together[:6] == alone
+    dec = big.decode_stream(together, [len(s) for s in streams])
+    for a, b in zip(dec, streams):
+        assert np.array_equal(a, b)
+
+
+def test_nc05_container_round_trip(setup):
+    _, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    from paper_2602_19626_amd import container as ct
+    cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32", skip=WL.skip,
+                         mix_init=WL.mix_init, max_streams=3)
+    ctx = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+    streams = [toks[:500], toks[500:777], toks[777:780]]
+    blob = ct.compress(ctx, streams, ct.config_flags(ctx.cfg))
+    flags, tau, chunks = ct.unpack(blob)
+    assert flags == ct.config_flags(ctx.cfg) and tau == 1.0
+    assert [c.n_tokens for c in chunks] == [len(s) for s in streams]
+    out = ct.decompress(ctx, blob)
+    for a, b in zip(out, streams):
+        assert np.array_equal(a, b)
