@@ -210,6 +210,51 @@ nc_status nc_profile(nc_ctx* ctx, int32_t kernel_class);
 /* Counters of the profiled class since nc_profile(). */
 nc_status nc_profile_read(nc_ctx* ctx, nc_kstat* out);
 
+/* ---- launch-shape autotuner ------------------------------------------------------------------
+ * Each transformer GEMM can run in several launch shapes: a split kernel (one workgroup per
+ * group of 16-column blocks and 16 mb rows, with `waves` waves dealing the 64-wide K parts), two
+ * LDS-staged tile kernels and, in BF16 / FP8, a 128 x 128 tile kernel.  All shapes evaluate the
+ * same per-part MFMA chains and add them in the same order, so the choice never changes a bit
+ * of any result; it only changes the speed.  Without tuning, a fixed rule on the row count
+ * picks the shape.
+ *
+ * nc_autotune times, with HIP events on the library's stream, the fixed rule and every fitting
+ * shape of each GEMM (QKV, O, gate/up, down, output layer) at the top of each row bucket
+ * (1, 2, 4, 8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1024, ... rows) up to max_rows (the
+ * output layer up to max_streams), `reps` launches per shape after two warm-up launches, and
+ * keeps the fastest shape per (GEMM, bucket) for every later call on this context.  It writes
+ * scratch rows into the pass buffers and stream 0's KV cache, so afterwards every stream must be
+ * reset (nc_streams_reset; the coding calls reset by themselves).  out (host, may be NULL when
+ * cap is 0) receives up to cap entries, n_out (may be NULL) the number of (GEMM, bucket) pairs
+ * measured.  Errors: NC_E_INVALID for max_rows outside [1, 2^20] or reps outside [1, 1000]. */
+enum {
+  NC_G_QKV = 0,
+  NC_G_OPROJ = 1,
+  NC_G_GATEUP = 2,
+  NC_G_DOWN = 3,
+  NC_G_LMHEAD = 4,
+  NC_G_COUNT = 5
+};
+typedef struct nc_tile {
+  int32_t gemm;      /* NC_G_* */
+  int32_t max_rows;  /* the bucket's top row count (the rows it was timed at) */
+  int32_t kind;      /* 0 fixed rule, 1 split, 2 small tile, 3 64 x 64 tile, 4 128 x 128 tile */
+  int32_t mb;        /* split: 16-row blocks per workgroup */
+  int32_t waves;     /* split: waves per workgroup */
+  float us_best;     /* measured time of the chosen shape per launch, microseconds */
+  float us_default;  /* measured time of the fixed rule per launch, microseconds */
+} nc_tile;
+nc_status nc_autotune(nc_ctx* ctx, uint32_t max_rows, uint32_t reps, nc_tile* out, uint32_t cap,
+                      uint32_t* n_out);
+/* Install n shapes (host array), e.g. a table saved from nc_autotune: entry i sets the shape of
+ * GEMM t[i].gemm for the row bucket that contains t[i].max_rows (kind 0 restores the fixed
+ * rule; us_* are ignored).  NC_E_INVALID for a bad id or kind, or a shape that does not fit the
+ * GEMM (a split shape outside 1..4 row blocks or 1..16 waves, or over the LDS budget; the
+ * 128 x 128 kernel in FP32 or for the QKV GEMM at head_dim 16); entries before it stay set. */
+nc_status nc_tiles_set(nc_ctx* ctx, const nc_tile* t, uint32_t n);
+/* Forget the measured shapes (back to the fixed rule). */
+nc_status nc_tiles_reset(nc_ctx* ctx);
+
 /* ---- host arithmetic coder (section 3.9), exposed for testing and container tools --------- */
 
 /* Encode n intervals (host, n x 2 uint32: cl, ch with 0 <= cl < ch <= total) with the 32-bit

@@ -185,6 +185,36 @@ class Context:
         check(lib().nc_decode_stream(self._h, n, ins, inb, lens, outp))
         return outs
 
+    def autotune(self, max_rows: int, reps: int = 10) -> list:
+        """Time every launch shape of each GEMM per row bucket up to max_rows and keep the
+        fastest (results are bit-identical across shapes).  Streams must be reset afterwards."""
+        from ._lib import GEMMS, TILE_KINDS, NcTile
+        cap = 5 * 32
+        arr = (NcTile * cap)()
+        n = C.c_uint32()
+        check(lib().nc_autotune(self._h, int(max_rows), int(reps), arr, cap, C.byref(n)))
+        out = []
+        for t in arr[:min(n.value, cap)]:
+            out.append({"gemm": GEMMS[t.gemm], "max_rows": t.max_rows, "kind": TILE_KINDS[t.kind],
+                        "mb": t.mb, "waves": t.waves, "us_best": t.us_best,
+                        "us_default": t.us_default})
+        return out
+
+    def tiles_set(self, entries):
+        """Install launch shapes: dicts with gemm, max_rows, kind (names as autotune() returns
+        them) and, for split shapes, mb and waves."""
+        from ._lib import GEMMS, TILE_KINDS, NcTile
+        arr = (NcTile * max(1, len(entries)))()
+        for i, e in enumerate(entries):
+            arr[i] = NcTile(GEMMS.index(e["gemm"]), int(e["max_rows"]),
+                            TILE_KINDS.index(e["kind"]), int(e.get("mb", 0)),
+                            int(e.get("waves", 0)), 0.0, 0.0)
+        check(lib().nc_tiles_set(self._h, arr, len(entries)))
+
+    def tiles_reset(self):
+        """Back to the fixed launch-shape rule."""
+        check(lib().nc_tiles_reset(self._h))
+
     def profile(self, kernel_class):
         """Time one kernel class with HIP events on the library's stream (None = off)."""
         from ._lib import KERNEL_CLASSES

@@ -42,6 +42,16 @@ class NcStats(C.Structure):
                 ("seconds", C.c_double), ("wait_seconds", C.c_double)]
 
 
+class NcTile(C.Structure):
+    _fields_ = [("gemm", C.c_int32), ("max_rows", C.c_int32), ("kind", C.c_int32),
+                ("mb", C.c_int32), ("waves", C.c_int32), ("us_best", C.c_float),
+                ("us_default", C.c_float)]
+
+
+GEMMS = ("qkv", "oproj", "gateup", "down", "lmhead")
+TILE_KINDS = ("rule", "split", "tile_small", "tile_64", "wide_128")
+
+
 class NcKstat(C.Structure):
     _fields_ = [("ms", C.c_double), ("launches", C.c_uint64), ("bytes", C.c_double),
                 ("flops", C.c_double)]
@@ -66,6 +76,10 @@ _SIG = {
     "nc_decode_stream": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P]),
     "nc_get_stats": (C.c_int, [_P, C.POINTER(NcStats)]),
     "nc_profile": (C.c_int, [_P, C.c_int32]),
+    "nc_autotune": (C.c_int, [_P, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint32,
+                              C.POINTER(C.c_uint32)]),
+    "nc_tiles_reset": (C.c_int, [_P]),
+    "nc_tiles_set": (C.c_int, [_P, C.c_void_p, C.c_uint32]),
     "nc_profile_read": (C.c_int, [_P, C.POINTER(NcKstat)]),
     "nc_ac_encode": (C.c_int, [_P, C.c_size_t, C.c_uint32, _P, C.c_size_t, _P, _P]),
     "nc_ac_decode_static": (C.c_int, [_P, C.c_size_t, _P, C.c_uint32, C.c_size_t, _P]),

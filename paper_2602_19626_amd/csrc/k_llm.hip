@@ -166,7 +166,7 @@ __device__ __forceinline__ void emit_qkv_prec(const GemmArgs& a, int prec_att, i
   } else {
     const int kv = n < nq + nk ? n - nq : n - nq - nk;
     const int kvh = kv / hd;
-    const long long slot = rm.pos % a.ring;
+    const long long slot = rm.slot;
     const long long sb = (long long)rm.stream * a.kv_stride + (long long)kvh * a.ring * hd;
     if (n < nq + nk) {
       idx = sb + slot * hd + within;
@@ -224,12 +224,12 @@ __device__ __forceinline__ void emit_qkv4_bf16(const GemmArgs& a, int m, int n, 
     for (int e = 0; e < 4; ++e)
       if (ok[e]) {
         const long long sb = (long long)rm[e].stream * a.kv_stride + (long long)kvh * a.ring * hd;
-        Kc[sb + (long long)(rm[e].pos % a.ring) * hd + within] = h[e];
+        Kc[sb + (long long)rm[e].slot * hd + within] = h[e];
       }
     return;
   }
   uint16_t* Vt = static_cast<uint16_t*>(a.vt_cache);
-  const int slot0 = rm[0].pos % a.ring;
+  const int slot0 = rm[0].slot;
   bool run = ok[3] && (slot0 & 3) == 0 && slot0 + 3 < a.ring;
 #pragma unroll
   for (int e = 1; e < 4; ++e)
@@ -246,7 +246,7 @@ __device__ __forceinline__ void emit_qkv4_bf16(const GemmArgs& a, int m, int n, 
   for (int e = 0; e < 4; ++e)
     if (ok[e]) {
       const long long sb = (long long)rm[e].stream * a.kv_stride + (long long)kvh * a.ring * hd;
-      Vt[sb + (long long)within * a.ring + rm[e].pos % a.ring] = h[e];
+      Vt[sb + (long long)within * a.ring + rm[e].slot] = h[e];
     }
 }
 
@@ -725,49 +725,67 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   const int fr = lane & 15, fg = lane >> 4;
   const int K = a.K, N = a.N;
   const int S = (K + KP - 1) / KP;
-  const int gi = blockIdx.x, r0 = blockIdx.y * SPLIT_ROWS;
-  const int M = min(a.M - r0, SPLIT_ROWS);
+  const int gi = blockIdx.x, r0 = blockIdx.y * MB * 16;
+  const int M = min(a.M - r0, MB * 16);
   const int gs = group_size(EPI, a.hd);
   float* s_inv = lds + S * gs * MB * 256;
   const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
   const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
-  // row scales first: their loads overlap the operand loads below
-  for (int m = threadIdx.x; m < M; m += blockDim.x)
-    s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
-  for (int s = wave; s < S; s += nw) {
+  // residual GEMMs include the long-K down projection, whose waves own two parts: there the
+  // second part's loads go out with the first's (a second register buffer)
+  constexpr int NBUF = EPI == E_RESID ? 2 : 1;
+  typename Frag<P>::T bf[NBUF][2], af[NBUF][MB];
+  auto load_part = [&](int s, int q) {
     const int k0 = s * KP;
-    typename Frag<P>::T bf[2], af[MB];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int n = group_block(EPI, a.hd, gi, j) * 16 + fr;
       if (j < gs && n < N)
-        Frag<P>::load_raw(bf[j], W8 + (long long)n * K * ES, k0, K, fg);
+        Frag<P>::load_raw(bf[q][j], W8 + (long long)n * K * ES, k0, K, fg);
       else
-        Frag<P>::zero(bf[j]);
+        Frag<P>::zero(bf[q][j]);
     }
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
       const int m = rb * 16 + fr;
       if (m < M) {
         const int ar = a.a_rows ? a.a_rows[r0 + m] : r0 + m;
-        Frag<P>::load_raw(af[rb], A8 + (long long)ar * K * ES, k0, K, fg);
+        Frag<P>::load_raw(af[q][rb], A8 + (long long)ar * K * ES, k0, K, fg);
       } else {
-        Frag<P>::zero(af[rb]);
+        Frag<P>::zero(af[q][rb]);
       }
     }
+  };
+  auto compute_part = [&](int s, int q) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (j >= gs) break;
 #pragma unroll
       for (int rb = 0; rb < MB; ++rb) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        Frag<P>::mma(acc, af[rb], bf[j]);
+        Frag<P>::mma(acc, af[q][rb], bf[q][j]);
         float* dst = lds + (((s * gs + j) * MB + rb) << 8);
 #pragma unroll
         for (int e = 0; e < 4; ++e) dst[(fg * 4 + e) * 16 + fr] = acc[e];
       }
     }
+  };
+  // parts wave, wave + nw, ...
+  if constexpr (NBUF == 2) {
+    for (int s = wave; s < S; s += 2 * nw) {
+      load_part(s, 0);
+      if (s + nw < S) load_part(s + nw, NBUF - 1);
+      compute_part(s, 0);
+      if (s + nw < S) compute_part(s + nw, NBUF - 1);
+    }
+  } else {
+    for (int s = wave; s < S; s += nw) {
+      load_part(s, 0);
+      compute_part(s, 0);
+    }
   }
+  for (int m = threadIdx.x; m < M; m += blockDim.x)
+    s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
   __syncthreads();
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
   // output (row m of the chunk, block j, column c) = (partials summed in part order) * deq * scale
@@ -968,8 +986,14 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
   const int hd = a.hd, nhb = hd / 16;
   const long long sbase = (long long)it.stream * a.kv_stride + (long long)it.kvh * a.ring * hd;
   const int key0 = chunk * KCH;
+  // ring slot of key key0 + off (0 <= off < 64 <= ring): one wave-uniform modulo per chunk
+  const int base = key0 % a.ring;
+  auto slot_of = [&](int off) {
+    const int t = base + off;
+    return t >= a.ring ? t - a.ring : t;
+  };
   // V^T operand of this lane: keys key0 + 16 grp .. + 15 (never wrapping: ring % 16 == 0)
-  const int vslot = (key0 + 16 * grp) % a.ring;
+  const int vslot = slot_of(16 * grp);
   v4f st[4];
   ChunkState r;
 #pragma unroll
@@ -982,7 +1006,7 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
     v4i vf[HDMAX / 16][2];  // 16 keys per lane per hd block
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const long long ks = sbase + (long long)((key0 + chunk_key(b, col)) % a.ring) * hd;
+      const long long ks = sbase + (long long)slot_of(chunk_key(b, col)) * hd;
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int k = s * 32 + grp * 8;
@@ -1027,7 +1051,7 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
     v4f kf[4][4], vf[HDMAX / 16][4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const long long ks = sbase + (long long)((key0 + chunk_key(b, col)) % a.ring) * hd;
+      const long long ks = sbase + (long long)slot_of(chunk_key(b, col)) * hd;
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
         const int k = 16 * grp + 4 * qd;
@@ -1275,23 +1299,28 @@ static void launch_split(dim3 grid, dim3 block, size_t lds, const GemmArgs& a, h
   hipLaunchKernelGGL((gemm_split_kernel<P, AM, EPI, MB>), grid, block, lds, s, a);
 }
 
-static int split_mb(int M) { return std::min((M + 15) / 16, SPLIT_ROWS / 16); }
+// Row blocks (16 rows each) per workgroup: GEMMs with few column groups cut M finer, so that
+// more workgroups share the work and each one's chain of loads, MFMAs and epilogue is shorter.
+static int split_mb(const GemmArgs& a, int epi) {
+  const int nblk = (a.N + 15) / 16, gs = group_size(epi, a.hd);
+  const int ngroups = (nblk + gs - 1) / gs;
+  const int cap = ngroups < 64 ? 1 : ngroups < 128 ? 2 : SPLIT_ROWS / 16;
+  return std::min((a.M + 15) / 16, cap);
+}
 
-static size_t split_lds(const GemmArgs& a, int epi) {
-  const int S = (a.K + KP - 1) / KP;
-  return (size_t(S) * group_size(epi, a.hd) * split_mb(a.M) * 256 + SPLIT_ROWS) * sizeof(float);
+static int split_parts(const GemmArgs& a) { return (a.K + KP - 1) / KP; }
+
+static size_t split_lds(const GemmArgs& a, int epi, int mb) {
+  return (size_t(split_parts(a)) * group_size(epi, a.hd) * mb * 256 + SPLIT_ROWS) * sizeof(float);
 }
 
 template <int P, int AM, int EPI>
-static void gemm_split(const GemmArgs& a, hipStream_t s) {
-  const int S = (a.K + KP - 1) / KP;
+static void gemm_split(const GemmArgs& a, hipStream_t s, int mb, int waves) {
   const int nblk = (a.N + 15) / 16;
   const int gs = group_size(EPI, a.hd);
   const int ngroups = (nblk + gs - 1) / gs;
-  const int mb = split_mb(a.M);
-  const int waves = S < SPLIT_WAVES ? S : SPLIT_WAVES;
-  const dim3 grid(ngroups, (a.M + SPLIT_ROWS - 1) / SPLIT_ROWS), block(64 * waves);
-  const size_t lds = split_lds(a, EPI);
+  const dim3 grid(ngroups, (a.M + 16 * mb - 1) / (16 * mb)), block(64 * waves);
+  const size_t lds = split_lds(a, EPI, mb);
   switch (mb) {
     case 1: launch_split<P, AM, EPI, 1>(grid, block, lds, a, s); break;
     case 2: launch_split<P, AM, EPI, 2>(grid, block, lds, a, s); break;
@@ -1306,20 +1335,72 @@ void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s) {
   NC_HIP(hipGetLastError());
 }
 
+static bool wide_ok(int prec, int epi, const GemmArgs& a) {
+  return prec != P_F32 && (epi != E_QKV || a.hd == 32 || a.hd == 64);
+}
+
+static bool tile_valid(int prec, int epi, const GemmArgs& a, const GemmTile& t) {
+  switch (t.kind) {
+    case T_AUTO: return true;
+    case T_SPLIT:
+      return t.mb >= 1 && t.mb <= SPLIT_ROWS / 16 && t.waves >= 1 && t.waves <= SPLIT_WAVES &&
+             split_lds(a, epi, t.mb) <= kSplitLdsMax;
+    case T_TILE_S:
+    case T_TILE_M: return true;
+    case T_WIDE: return wide_ok(prec, epi, a);
+    default: return false;
+  }
+}
+
+// The fixed rule used when no measured choice is given.
+static GemmTile default_tile(int prec, int epi, const GemmArgs& a) {
+  const int S = split_parts(a);
+  const GemmTile sp{T_SPLIT, split_mb(a, epi), S < SPLIT_WAVES ? S : SPLIT_WAVES};
+  if (a.M < SKINNY_ROWS && split_lds(a, epi, sp.mb) <= kSplitLdsMax) return sp;
+  if (a.M >= SKINNY_ROWS && wide_ok(prec, epi, a)) return GemmTile{T_WIDE, 0, 0};
+  return GemmTile{a.M <= 64 ? T_TILE_S : T_TILE_M, 0, 0};
+}
+
+bool gemm_tile_fits(int prec, int epi, const GemmArgs& a, const GemmTile& t) {
+  return tile_valid(prec, epi, a, t);
+}
+
+std::vector<GemmTile> gemm_candidates(int prec, int epi, const GemmArgs& a) {
+  std::vector<GemmTile> out;
+  const int S = split_parts(a);
+  const int wmax = S < SPLIT_WAVES ? S : SPLIT_WAVES;
+  if (a.M <= 1024) {
+    const int mbmax = std::min((a.M + 15) / 16, SPLIT_ROWS / 16);
+    for (int mb = 1; mb <= mbmax; ++mb) {
+      int prev = 0;
+      for (int div = 1; div <= 4; div *= 2) {
+        const int w = (wmax + div - 1) / div;
+        const GemmTile t{T_SPLIT, mb, w};
+        if (w != prev && tile_valid(prec, epi, a, t)) out.push_back(t);
+        prev = w;
+      }
+    }
+  }
+  out.push_back(GemmTile{T_TILE_S, 0, 0});
+  out.push_back(GemmTile{T_TILE_M, 0, 0});
+  if (wide_ok(prec, epi, a)) out.push_back(GemmTile{T_WIDE, 0, 0});
+  return out;
+}
+
 template <int P, int AM, int EPI>
-static void gemm_shape(const GemmArgs& a, hipStream_t s) {
-  if (a.M < SKINNY_ROWS && split_lds(a, EPI) <= kSplitLdsMax) return gemm_split<P, AM, EPI>(a, s);
+static void gemm_shape(const GemmArgs& a, hipStream_t s, GemmTile t) {
+  if (t.kind == T_AUTO) t = default_tile(P, EPI, a);
+  if (t.kind == T_SPLIT) return gemm_split<P, AM, EPI>(a, s, t.mb, t.waves);
   if constexpr (P != P_F32) {
-    if (a.M >= SKINNY_ROWS && (EPI != E_QKV || a.hd == 32 || a.hd == 64))
-      return gemm_wide<P, AM, EPI>(a, s);
+    if (t.kind == T_WIDE) return gemm_wide<P, AM, EPI>(a, s);
   }
   if constexpr (EPI == E_GLU) {
-    if (a.M <= 64)
+    if (t.kind == T_TILE_S)
       gemm_go<P, AM, EPI, 16, 32, 1, 2>(a, s);
     else
       gemm_go<P, AM, EPI, 32, 32, 2, 2>(a, s);
   } else {
-    if (a.M <= 64)
+    if (t.kind == T_TILE_S)
       gemm_go<P, AM, EPI, 16, 16, 1, 4>(a, s);
     else
       gemm_go<P, AM, EPI, 32, 32, 2, 2>(a, s);
@@ -1327,21 +1408,21 @@ static void gemm_shape(const GemmArgs& a, hipStream_t s) {
 }
 
 template <int P>
-static void gemm_prec(int amode, int epi, const GemmArgs& a, hipStream_t s) {
+static void gemm_prec(int amode, int epi, const GemmArgs& a, hipStream_t s, GemmTile t) {
   if (amode == A_NORM) {
     switch (epi) {
-      case E_STORE: return gemm_shape<P, A_NORM, E_STORE>(a, s);
-      case E_GLU: return gemm_shape<P, A_NORM, E_GLU>(a, s);
-      case E_QKV: return gemm_shape<P, A_NORM, E_QKV>(a, s);
+      case E_STORE: return gemm_shape<P, A_NORM, E_STORE>(a, s, t);
+      case E_GLU: return gemm_shape<P, A_NORM, E_GLU>(a, s, t);
+      case E_QKV: return gemm_shape<P, A_NORM, E_QKV>(a, s, t);
       default: break;
     }
   } else if (epi == E_RESID) {
-    return gemm_shape<P, A_DIRECT, E_RESID>(a, s);
+    return gemm_shape<P, A_DIRECT, E_RESID>(a, s, t);
   }
   fail(NC_E_INVALID, "unsupported GEMM variant");
 }
 
-void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s) {
+void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s, GemmTile t) {
   if (a.M <= 0) return;
   NC_CHECK(a.K % 16 == 0, NC_E_INVALID, "GEMM K must be a multiple of 16");
   if (epi == E_QKV) NC_CHECK(64 % a.hd == 0, NC_E_INVALID, "head_dim must divide 64");
@@ -1349,12 +1430,13 @@ void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s)
   if (amode == A_NORM) NC_CHECK(a.ssq || a.inv, NC_E_INVALID, "normed GEMM needs row statistics");
   if (epi == E_RESID)
     NC_CHECK(a.N % 16 == 0 && (!a.y_out || a.y_gain), NC_E_INVALID, "bad residual epilogue");
+  NC_CHECK(tile_valid(prec, epi, a, t), NC_E_INVALID, "GEMM launch shape does not fit this GEMM");
   if (prec == P_F32)
-    gemm_prec<P_F32>(amode, epi, a, s);
+    gemm_prec<P_F32>(amode, epi, a, s, t);
   else if (prec == P_BF16)
-    gemm_prec<P_BF16>(amode, epi, a, s);
+    gemm_prec<P_BF16>(amode, epi, a, s, t);
   else
-    gemm_prec<P_FP8>(amode, epi, a, s);
+    gemm_prec<P_FP8>(amode, epi, a, s, t);
   NC_HIP(hipGetLastError());
 }
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace nc {
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
@@ -17,7 +19,7 @@ struct RowMeta {
   int32_t stream;
   int32_t pos;
   int32_t tok;
-  int32_t pad;
+  int32_t slot;  // pos mod ring: the KV-ring slot of this position (filled by the host)
 };
 
 // Arguments of one GEMM C[M][N] = A[M][K] W[N][K]^T (+ epilogue).
@@ -83,7 +85,25 @@ struct AttnArgs {
   size_t ws_bytes;
 };
 
-void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s);
+// Launch shape of one GEMM.  Every shape evaluates the same per-part MFMA chains and adds them in
+// the same order, so the choice changes the speed only, never a bit of the result.
+enum GemmKind {
+  T_AUTO = 0,    // the fixed size rule
+  T_SPLIT = 1,   // a workgroup per (epilogue group, mb row blocks); waves deal the K parts
+  T_TILE_S = 2,  // LDS-staged tiles, small (16 x 64, or 16 x 64 gate/up pairs)
+  T_TILE_M = 3,  // LDS-staged tiles, 64 x 64
+  T_WIDE = 4,    // 128 x 128 tiles with XCD-aware order (BF16 / FP8 only)
+};
+struct GemmTile {
+  int kind = T_AUTO;
+  int mb = 0;     // T_SPLIT: 16-row blocks per workgroup (1..4)
+  int waves = 0;  // T_SPLIT: waves per workgroup (1..16)
+};
+void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s,
+                 GemmTile t = GemmTile{});
+bool gemm_tile_fits(int prec, int epi, const GemmArgs& a, const GemmTile& t);
+// Every launch shape that fits this GEMM (the autotuner's search space).
+std::vector<GemmTile> gemm_candidates(int prec, int epi, const GemmArgs& a);
 // RMSNorm scale of rows a_rows[m] (from a.ssq) into inv[a_rows[m]]
 void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s);
 void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parallel,

@@ -53,6 +53,18 @@ size_t prec_bytes(int p) { return p == P_F32 ? 4 : p == P_BF16 ? 2 : 1; }
 
 }  // namespace
 
+// Row-count buckets of the launch-shape table: bucket i holds row counts in
+// (kRowBucketHi[i - 1], kRowBucketHi[i]].
+constexpr int kRowBuckets = 21;
+constexpr int kRowBucketHi[kRowBuckets] = {1,    2,    4,    8,    16,   32,    48,
+                                           64,   96,   128,  192,  256,  384,   512,
+                                           1024, 2048, 4096, 8192, 16384, 32768, 1 << 30};
+static int row_bucket(int M) {
+  int i = 0;
+  while (i + 1 < kRowBuckets && M > kRowBucketHi[i]) ++i;
+  return i;
+}
+
 struct nc_ctx {
   nc_config cfg{};
   int prec = P_F32, att = P_F32;
@@ -121,6 +133,8 @@ struct nc_ctx {
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_busy;
   hipEvent_t ev_open = nullptr;
+  // measured GEMM launch shapes per (GEMM, row bucket); kind T_AUTO = the fixed rule
+  GemmTile tiles[NC_G_COUNT][kRowBuckets];
 
   ~nc_ctx();
 };
@@ -226,6 +240,12 @@ void prof_end(nc_ctx* c, int cls, double bytes, double flops) {
   c->prof.bytes += bytes;
   c->prof.flops += flops;
   if (c->ev_busy.size() > 4096) sync(c);
+}
+
+// The measured launch shape of a GEMM at M rows (the calibration pass runs in float32, whose
+// shapes are not tuned, and keeps the fixed rule).
+GemmTile tile_for(const nc_ctx* c, bool calib, int gemm, int M) {
+  return calib ? GemmTile{} : c->tiles[gemm][row_bucket(M)];
 }
 
 double gemm_bytes(const GemmArgs& a, int amode, int epi, int prec, int att) {
@@ -363,6 +383,7 @@ struct PassPlan {
 PassPlan plan_pass(nc_ctx* c, std::vector<RowMeta> rows, bool calib = false) {
   PassPlan p;
   p.rows = std::move(rows);
+  for (RowMeta& r : p.rows) r.slot = r.pos % c->R;
   const std::vector<RowMeta>& R = p.rows;
   const int n = int(R.size());
   const int g = c->hq / c->hk;
@@ -439,49 +460,142 @@ __global__ void copy_rows_kernel(const uint32_t* y, const float* yinv, const int
   if (threadIdx.x == 0) oinv[t] = yinv[s];
 }
 
+// Arguments of the five GEMMs of a pass over n rows (layer l; calib: the float32 calibration
+// pass, which also records activation maxima in am).
+static float op_inv_scale(int prec, float sc) { return prec == P_FP8 ? 1.0f / sc : 1.0f; }
+
+static long long layer_kv_bytes(const nc_ctx* c) {
+  return (long long)c->S_alloc * c->kv_stride * prec_bytes(c->att);
+}
+
+GemmArgs args_qkv(nc_ctx* c, int l, int n, const RowMeta* drows, bool calib) {
+  Layer& L = c->layers[l];
+  GemmArgs a{};
+  a.M = n;
+  a.N = (c->hq + 2 * c->hk) * c->hd;
+  a.K = c->d;
+  a.A = c->yb.p;
+  a.eps = c->cfg.norm_eps;
+  a.a_scale = L.sa_qkv;
+  a.W = calib ? (void*)L.Wqkv32 : L.Wqkv;
+  a.w_scale = calib ? 1.f : L.sw_qkv;
+  a.rows = drows;
+  a.rope = c->rope.p;
+  a.q_out = c->qb.p;
+  a.k_cache = c->kc.p + l * layer_kv_bytes(c);
+  a.vt_cache = c->vc.p + l * layer_kv_bytes(c);
+  a.kv_stride = c->kv_stride;
+  a.Hq = c->hq;
+  a.Hk = c->hk;
+  a.hd = c->hd;
+  a.ring = c->R;
+  a.ssq = c->xss.p;
+  return a;
+}
+
+GemmArgs args_oproj(nc_ctx* c, int l, int n, bool calib, float* am) {
+  Layer& L = c->layers[l];
+  const int prec = calib ? P_F32 : c->prec;
+  GemmArgs ob{};
+  ob.M = n;
+  ob.N = c->d;
+  ob.K = c->hq * c->hd;
+  ob.A = c->ob.p;
+  ob.a_scale = L.sa_o;
+  ob.W = calib ? (void*)L.Wo32 : L.Wo;
+  ob.w_scale = calib ? 1.f : L.sw_o;
+  ob.out_f32 = c->x.p;
+  ob.ldo = c->d;
+  ob.ssq_out = c->xss.p;
+  ob.y_out = c->yb.p;
+  ob.y_gain = L.g_mlp;
+  ob.y_inv_scale = op_inv_scale(prec, L.sa_gu);
+  ob.y_amax = am ? am + 2 : nullptr;
+  return ob;
+}
+
+GemmArgs args_gateup(nc_ctx* c, int l, int n, bool calib, float* am) {
+  Layer& L = c->layers[l];
+  GemmArgs gu{};
+  gu.M = n;
+  gu.N = 2 * c->F;
+  gu.K = c->d;
+  gu.A = c->yb.p;
+  gu.eps = c->cfg.norm_eps;
+  gu.a_scale = L.sa_gu;
+  gu.W = calib ? (void*)L.Wgu32 : L.Wgu;
+  gu.w_scale = calib ? 1.f : L.sw_gu;
+  gu.out_p = c->hb.p;
+  gu.out_scale = L.sa_d;
+  gu.out_amax = am ? am + 3 : nullptr;
+  gu.ssq = c->xss.p;
+  return gu;
+}
+
+GemmArgs args_down(nc_ctx* c, int l, int n, bool calib) {
+  Layer& L = c->layers[l];
+  const int prec = calib ? P_F32 : c->prec;
+  GemmArgs dn{};
+  dn.M = n;
+  dn.N = c->d;
+  dn.K = c->F;
+  dn.A = c->hb.p;
+  dn.a_scale = L.sa_d;
+  dn.W = calib ? (void*)L.Wd32 : L.Wd;
+  dn.w_scale = calib ? 1.f : L.sw_d;
+  dn.out_f32 = c->x.p;
+  dn.ldo = c->d;
+  dn.ssq_out = c->xss.p;
+  // the next normed GEMM: the next layer's QKV, or the output layer
+  const bool last = l + 1 == c->nl;
+  dn.y_out = c->yb.p;
+  dn.y_gain = last ? c->g_final : c->layers[l + 1].g_attn;
+  dn.y_inv_scale = op_inv_scale(prec, last ? c->sa_lm : c->layers[l + 1].sa_qkv);
+  dn.y_amax = calib ? c->amax.p + 4 * (l + 1) : nullptr;
+  return dn;
+}
+
+// z[m] = final_norm(x) E^T for m < M, from the operand rows A[a_rows[m]] = quantise(x * g_final)
+// and their RMSNorm scales Ainv[a_rows[m]].
+GemmArgs args_lm(nc_ctx* c, const void* A, const float* Ainv, const int32_t* a_rows, int M,
+                 float* zout, bool calib) {
+  GemmArgs a{};
+  a.M = M;
+  a.N = c->V;
+  a.K = c->d;
+  a.A = A;
+  a.a_rows = a_rows;
+  a.eps = c->cfg.norm_eps;
+  a.a_scale = c->sa_lm;
+  a.W = calib ? (void*)c->E32 : c->Elm;
+  a.w_scale = calib ? 1.f : c->sw_lm;
+  a.out_f32 = zout;
+  a.ldo = c->V;
+  a.inv = Ainv;
+  return a;
+}
+
 // Appends a planned pass to the KV caches; leaves each row's final residual in x, its
-// output-layer operand in yb, and each stream's newest operand row in hlast.  Rows of one stream are consecutive positions spanning fewer than
-// `slide` positions (the ring holds ctx_len + slide entries, so no needed key is overwritten).
+// output-layer operand in yb, and each stream's newest operand row in hlast.  Rows of one stream
+// are consecutive positions spanning fewer than `slide` positions (the ring holds at least
+// ctx_len + slide entries, so no needed key is overwritten).
 void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = {}) {
   const int n = int(p.rows.size());
   if (!n) return;
   ensure_rows(c, n);
   const RowMeta* drows = reinterpret_cast<const RowMeta*>(dstage + p.off_rows);
   const AttnItem* ditems = reinterpret_cast<const AttnItem*>(dstage + p.off_items);
-  const int g = c->hq / c->hk;
-  (void)g;
   const int prec = o.calib ? P_F32 : c->prec;
   const int att = o.calib ? P_F32 : c->att;
-  auto inv_scale = [&](float sc) { return prec == P_FP8 ? 1.0f / sc : 1.0f; };
   launch_embed(c->E32, drows, n, c->d, c->x.p, c->xss.p, c->yb.p, c->layers[0].g_attn, prec,
-               inv_scale(c->layers[0].sa_qkv), o.calib ? c->amax.p : nullptr, c->st);
-  const long long layer_kv = (long long)c->S_alloc * c->kv_stride * prec_bytes(c->att);
+               op_inv_scale(prec, c->layers[0].sa_qkv), o.calib ? c->amax.p : nullptr, c->st);
   for (int l = 0; l < c->nl; ++l) {
     Layer& L = c->layers[l];
     float* am = o.calib ? c->amax.p + 4 * l : nullptr;
     // QKV with RoPE and the KV-ring write
-    GemmArgs a{};
-    a.M = n;
-    a.N = (c->hq + 2 * c->hk) * c->hd;
-    a.K = c->d;
-    a.A = c->yb.p;
-    a.eps = c->cfg.norm_eps;
-    a.a_scale = L.sa_qkv;
-    a.W = o.calib ? (void*)L.Wqkv32 : L.Wqkv;
-    a.w_scale = o.calib ? 1.f : L.sw_qkv;
-    a.rows = drows;
-    a.rope = c->rope.p;
-    a.q_out = c->qb.p;
-    a.k_cache = c->kc.p + l * layer_kv;
-    a.vt_cache = c->vc.p + l * layer_kv;
-    a.kv_stride = c->kv_stride;
-    a.Hq = c->hq;
-    a.Hk = c->hk;
-    a.hd = c->hd;
-    a.ring = c->R;
-    a.ssq = c->xss.p;
+    const GemmArgs a = args_qkv(c, l, n, drows, o.calib);
     prof_begin(c, NC_K_QKV);
-    launch_gemm(prec, A_NORM, E_QKV, a, c->st);
+    launch_gemm(prec, A_NORM, E_QKV, a, c->st, tile_for(c, o.calib, NC_G_QKV, n));
     prof_end(c, NC_K_QKV, gemm_bytes(a, A_NORM, E_QKV, prec, att), 2.0 * a.M * a.N * a.K);
     // attention
     AttnArgs t{};
@@ -511,61 +625,19 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     launch_attention(att, prec, t, par, c->st);
     prof_end(c, NC_K_ATTN, p.attn_bytes, p.attn_flops);
     // O projection + residual
-    GemmArgs ob{};
-    ob.M = n;
-    ob.N = c->d;
-    ob.K = c->hq * c->hd;
-    ob.A = c->ob.p;
-    ob.a_scale = L.sa_o;
-    ob.W = o.calib ? (void*)L.Wo32 : L.Wo;
-    ob.w_scale = o.calib ? 1.f : L.sw_o;
-    ob.out_f32 = c->x.p;
-    ob.ldo = c->d;
-    ob.ssq_out = c->xss.p;
-    ob.y_out = c->yb.p;
-    ob.y_gain = L.g_mlp;
-    ob.y_inv_scale = inv_scale(L.sa_gu);
-    ob.y_amax = am ? am + 2 : nullptr;
+    const GemmArgs ob = args_oproj(c, l, n, o.calib, am);
     prof_begin(c, NC_K_OPROJ);
-    launch_gemm(prec, A_DIRECT, E_RESID, ob, c->st);
+    launch_gemm(prec, A_DIRECT, E_RESID, ob, c->st, tile_for(c, o.calib, NC_G_OPROJ, n));
     prof_end(c, NC_K_OPROJ, gemm_bytes(ob, A_DIRECT, E_RESID, prec, att), 2.0 * n * ob.N * ob.K);
     // gate/up with SiLU
-    GemmArgs gu{};
-    gu.M = n;
-    gu.N = 2 * c->F;
-    gu.K = c->d;
-    gu.A = c->yb.p;
-    gu.eps = c->cfg.norm_eps;
-    gu.a_scale = L.sa_gu;
-    gu.W = o.calib ? (void*)L.Wgu32 : L.Wgu;
-    gu.w_scale = o.calib ? 1.f : L.sw_gu;
-    gu.out_p = c->hb.p;
-    gu.out_scale = L.sa_d;
-    gu.out_amax = am ? am + 3 : nullptr;
-    gu.ssq = c->xss.p;
+    const GemmArgs gu = args_gateup(c, l, n, o.calib, am);
     prof_begin(c, NC_K_GATEUP);
-    launch_gemm(prec, A_NORM, E_GLU, gu, c->st);
+    launch_gemm(prec, A_NORM, E_GLU, gu, c->st, tile_for(c, o.calib, NC_G_GATEUP, n));
     prof_end(c, NC_K_GATEUP, gemm_bytes(gu, A_NORM, E_GLU, prec, att), 2.0 * n * gu.N * gu.K);
     // down projection + residual
-    GemmArgs dn{};
-    dn.M = n;
-    dn.N = c->d;
-    dn.K = c->F;
-    dn.A = c->hb.p;
-    dn.a_scale = L.sa_d;
-    dn.W = o.calib ? (void*)L.Wd32 : L.Wd;
-    dn.w_scale = o.calib ? 1.f : L.sw_d;
-    dn.out_f32 = c->x.p;
-    dn.ldo = c->d;
-    dn.ssq_out = c->xss.p;
-    // the next normed GEMM: the next layer's QKV, or the output layer
-    const bool last = l + 1 == c->nl;
-    dn.y_out = c->yb.p;
-    dn.y_gain = last ? c->g_final : c->layers[l + 1].g_attn;
-    dn.y_inv_scale = inv_scale(last ? c->sa_lm : c->layers[l + 1].sa_qkv);
-    dn.y_amax = o.calib ? c->amax.p + 4 * (l + 1) : nullptr;
+    const GemmArgs dn = args_down(c, l, n, o.calib);
     prof_begin(c, NC_K_DOWN);
-    launch_gemm(prec, A_DIRECT, E_RESID, dn, c->st);
+    launch_gemm(prec, A_DIRECT, E_RESID, dn, c->st, tile_for(c, o.calib, NC_G_DOWN, n));
     prof_end(c, NC_K_DOWN, gemm_bytes(dn, A_DIRECT, E_RESID, prec, att), 2.0 * n * dn.N * dn.K);
   }
   const int nl = int(p.last.size() / 2);
@@ -587,26 +659,12 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
   c->stats.body_rows += n;
 }
 
-// z[m] = final_norm(x) E^T for m < M, from the operand rows A[a_rows[m]] = quantise(x * g_final)
-// and their RMSNorm scales Ainv[a_rows[m]].
 void run_lm_head(nc_ctx* c, const void* A, const float* Ainv, const int32_t* a_rows, int M,
                  float* zout, bool calib = false) {
-  GemmArgs a{};
-  a.M = M;
-  a.N = c->V;
-  a.K = c->d;
-  a.A = A;
-  a.a_rows = a_rows;
-  a.eps = c->cfg.norm_eps;
-  a.a_scale = c->sa_lm;
-  a.W = calib ? (void*)c->E32 : c->Elm;
-  a.w_scale = calib ? 1.f : c->sw_lm;
-  a.out_f32 = zout;
-  a.ldo = c->V;
-  a.inv = Ainv;
+  const GemmArgs a = args_lm(c, A, Ainv, a_rows, M, zout, calib);
   const int prec = calib ? P_F32 : c->prec;
   prof_begin(c, NC_K_LMHEAD);
-  launch_gemm(prec, A_NORM, E_STORE, a, c->st);
+  launch_gemm(prec, A_NORM, E_STORE, a, c->st, tile_for(c, calib, NC_G_LMHEAD, M));
   prof_end(c, NC_K_LMHEAD, gemm_bytes(a, A_NORM, E_STORE, prec, c->att), 2.0 * M * a.N * a.K);
 }
 
@@ -1286,6 +1344,132 @@ nc_status nc_profile(nc_ctx* c, int32_t cls) {
     sync(c);
     c->prof_class = cls;
     c->prof = nc_kstat{};
+  });
+}
+
+nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out, uint32_t cap,
+                      uint32_t* n_out) {
+  return guard([&] {
+    NC_CHECK(c, NC_E_INVALID, "NULL context");
+    NC_CHECK(max_rows >= 1 && max_rows <= (1u << 20), NC_E_INVALID,
+             "max_rows must be in [1, 2^20]");
+    NC_CHECK(reps >= 1 && reps <= 1000, NC_E_INVALID, "reps must be in [1, 1000]");
+    NC_CHECK(out || cap == 0, NC_E_INVALID, "NULL output with nonzero capacity");
+    NC_HIP(hipSetDevice(c->dev));
+    sync(c);
+    if (c->S_alloc < 1) reset_streams(c, 1, 1);
+    const int Mmax = int(max_rows);
+    // output-layer GEMMs only ever see one row per stream
+    const int Mlm = std::min(Mmax, c->cfg.max_streams);
+    ensure_rows(c, Mmax);
+    ensure_step(c, Mlm);
+    // scratch rows: stream 0, consecutive positions inside the RoPE table and the ring
+    const int P = std::max(1, std::min(c->R, c->rope_pos));
+    std::vector<RowMeta> rows(Mmax);
+    for (int m = 0; m < Mmax; ++m) rows[m] = RowMeta{0, m % P, 0, (m % P) % c->R};
+    h2d(c, c->rowsd.p, rows.data(), rows.size());
+    NC_HIP(hipMemsetAsync(c->x.p, 0, c->x.n * sizeof(float), c->st));
+    NC_HIP(hipMemsetAsync(c->xss.p, 0, c->xss.n * sizeof(float), c->st));
+    NC_HIP(hipMemsetAsync(c->yb.p, 0, c->yb.n * sizeof(float), c->st));
+    NC_HIP(hipMemsetAsync(c->xinv.p, 0, c->xinv.n * sizeof(float), c->st));
+    NC_HIP(hipMemsetAsync(c->hb.p, 0, c->hb.n, c->st));
+    NC_HIP(hipMemsetAsync(c->ob.p, 0, c->ob.n, c->st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    NC_HIP(hipEventCreate(&e0));
+    NC_HIP(hipEventCreate(&e1));
+    struct Ev {
+      hipEvent_t a, b;
+      ~Ev() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } ev{e0, e1};
+    const int prec = c->prec;
+    uint32_t n = 0;
+    for (int g = 0; g < NC_G_COUNT; ++g) {
+      const int top = g == NC_G_LMHEAD ? Mlm : Mmax;
+      static const int kEpi[NC_G_COUNT] = {E_QKV, E_RESID, E_GLU, E_RESID, E_STORE};
+      static const int kAm[NC_G_COUNT] = {A_NORM, A_DIRECT, A_NORM, A_DIRECT, A_NORM};
+      for (int b = 0; b < kRowBuckets; ++b) {
+        const int lo = b ? kRowBucketHi[b - 1] + 1 : 1;
+        if (lo > top) {
+          c->tiles[g][b] = GemmTile{};
+          continue;
+        }
+        const int M = std::min(kRowBucketHi[b], top);
+        GemmArgs a;
+        switch (g) {
+          case NC_G_QKV: a = args_qkv(c, 0, M, c->rowsd.p, false); break;
+          case NC_G_OPROJ: a = args_oproj(c, 0, M, false, nullptr); break;
+          case NC_G_GATEUP: a = args_gateup(c, 0, M, false, nullptr); break;
+          case NC_G_DOWN: a = args_down(c, 0, M, false); break;
+          default: a = args_lm(c, c->yb.p, c->xinv.p, nullptr, M, c->z.p, false); break;
+        }
+        auto time_us = [&](const GemmTile& t) {
+          for (int w = 0; w < 2; ++w) launch_gemm(prec, kAm[g], kEpi[g], a, c->st, t);
+          NC_HIP(hipEventRecord(e0, c->st));
+          for (uint32_t r = 0; r < reps; ++r) launch_gemm(prec, kAm[g], kEpi[g], a, c->st, t);
+          NC_HIP(hipEventRecord(e1, c->st));
+          NC_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          NC_HIP(hipEventElapsedTime(&ms, e0, e1));
+          return 1000.f * ms / float(reps);
+        };
+        const float us_default = time_us(GemmTile{});
+        GemmTile best{};
+        float us_best = us_default;
+        for (const GemmTile& t : gemm_candidates(prec, kEpi[g], a)) {
+          const float u = time_us(t);
+          if (u < us_best) {
+            us_best = u;
+            best = t;
+          }
+        }
+        c->tiles[g][b] = best;
+        if (n < cap)
+          out[n] = nc_tile{g, kRowBucketHi[b] < top ? kRowBucketHi[b] : top, best.kind, best.mb,
+                           best.waves, us_best, us_default};
+        ++n;
+      }
+    }
+    sync(c);
+    // the scratch rows overwrote pass buffers and stream 0's cache: every stream needs a reset
+    c->n_streams = 0;
+    if (n_out) *n_out = n;
+  });
+}
+
+nc_status nc_tiles_set(nc_ctx* c, const nc_tile* t, uint32_t n) {
+  return guard([&] {
+    NC_CHECK(c && (t || n == 0), NC_E_INVALID, "NULL argument");
+    static const int kEpi[NC_G_COUNT] = {E_QKV, E_RESID, E_GLU, E_RESID, E_STORE};
+    for (uint32_t i = 0; i < n; ++i) {
+      const nc_tile& e = t[i];
+      NC_CHECK(e.gemm >= 0 && e.gemm < NC_G_COUNT, NC_E_INVALID, "entry %u: bad GEMM id", i);
+      NC_CHECK(e.max_rows >= 1, NC_E_INVALID, "entry %u: max_rows must be >= 1", i);
+      NC_CHECK(e.kind >= T_AUTO && e.kind <= T_WIDE, NC_E_INVALID, "entry %u: bad kind", i);
+      const GemmTile g{e.kind, e.mb, e.waves};
+      const int M = e.max_rows;
+      GemmArgs a;
+      switch (e.gemm) {
+        case NC_G_QKV: a = args_qkv(c, 0, M, nullptr, false); break;
+        case NC_G_OPROJ: a = args_oproj(c, 0, M, false, nullptr); break;
+        case NC_G_GATEUP: a = args_gateup(c, 0, M, false, nullptr); break;
+        case NC_G_DOWN: a = args_down(c, 0, M, false); break;
+        default: a = args_lm(c, nullptr, nullptr, nullptr, M, nullptr, false); break;
+      }
+      NC_CHECK(gemm_tile_fits(c->prec, kEpi[e.gemm], a, g), NC_E_INVALID,
+               "entry %u: launch shape does not fit this GEMM", i);
+      c->tiles[e.gemm][row_bucket(M)] = g;
+    }
+  });
+}
+
+nc_status nc_tiles_reset(nc_ctx* c) {
+  return guard([&] {
+    NC_CHECK(c, NC_E_INVALID, "NULL context");
+    for (auto& row : c->tiles)
+      for (auto& t : row) t = GemmTile{};
   });
 }
 
