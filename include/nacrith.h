@@ -199,14 +199,18 @@ enum {
   NC_K_COUNT = 8
 };
 typedef struct nc_kstat {
-  double ms;          /* summed event time of the launches */
-  uint64_t launches;
-  double bytes;       /* algorithmic bytes of those launches */
-  double flops;       /* algorithmic flops of those launches */
+  double ms;          /* summed event time of the timed launches */
+  uint64_t launches;  /* launches of the class */
+  uint64_t timed;     /* launches that were timed: the 1st, (stride+1)-th, ... */
+  double bytes;       /* algorithmic bytes of the timed launches */
+  double flops;       /* algorithmic flops of the timed launches */
 } nc_kstat;
 
-/* Select the profiled kernel class (-1 = off) and clear its counters. */
-nc_status nc_profile(nc_ctx* ctx, int32_t kernel_class);
+/* Select the profiled kernel class (-1 = off) and clear its counters.  Every stride-th launch
+ * of the class (stride >= 1) is bracketed by events, which bounds the cost of the event records
+ * on long runs; ms / timed is the class's average launch duration.  NC_E_INVALID for a bad class
+ * or stride 0. */
+nc_status nc_profile(nc_ctx* ctx, int32_t kernel_class, uint32_t stride);
 /* Counters of the profiled class since nc_profile(). */
 nc_status nc_profile_read(nc_ctx* ctx, nc_kstat* out);
 
@@ -221,7 +225,9 @@ nc_status nc_profile_read(nc_ctx* ctx, nc_kstat* out);
  * nc_autotune times, with HIP events on the library's stream, the fixed rule and every fitting
  * shape of each GEMM (QKV, O, gate/up, down, output layer) at the top of each row bucket
  * (1, 2, 4, 8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1024, ... rows) up to max_rows (the
- * output layer up to max_streams), `reps` launches per shape after two warm-up launches, and
+ * output layer up to max_streams), `reps` launches per shape after one warm-up launch, each
+ * timed alone right after a 512 MiB device write that evicts the weights from the caches (as the
+ * KV-cache stream of a pass does) and cycling through the layers' weights, and
  * keeps the fastest shape per (GEMM, bucket) for every later call on this context.  It writes
  * scratch rows into the pass buffers and stream 0's KV cache, so afterwards every stream must be
  * reset (nc_streams_reset; the coding calls reset by themselves).  out (host, may be NULL when

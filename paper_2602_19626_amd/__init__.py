@@ -215,11 +215,12 @@ class Context:
         """Back to the fixed launch-shape rule."""
         check(lib().nc_tiles_reset(self._h))
 
-    def profile(self, kernel_class):
-        """Time one kernel class with HIP events on the library's stream (None = off)."""
+    def profile(self, kernel_class, stride: int = 1):
+        """Time every stride-th launch of one kernel class with HIP events on the library's
+        stream (None = off)."""
         from ._lib import KERNEL_CLASSES
         cls = -1 if kernel_class is None else KERNEL_CLASSES[kernel_class]
-        check(lib().nc_profile(self._h, cls))
+        check(lib().nc_profile(self._h, cls, int(stride)))
 
     def profile_read(self) -> dict:
         from ._lib import NcKstat

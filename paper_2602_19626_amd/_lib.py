@@ -53,8 +53,8 @@ TILE_KINDS = ("rule", "split", "tile_small", "tile_64", "wide_128")
 
 
 class NcKstat(C.Structure):
-    _fields_ = [("ms", C.c_double), ("launches", C.c_uint64), ("bytes", C.c_double),
-                ("flops", C.c_double)]
+    _fields_ = [("ms", C.c_double), ("launches", C.c_uint64), ("timed", C.c_uint64),
+                ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 KERNEL_CLASSES = {"qkv": 0, "attn": 1, "oproj": 2, "gateup": 3, "down": 4, "lmhead": 5,
@@ -75,7 +75,7 @@ _SIG = {
     "nc_encode_stream": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P, _P, _P]),
     "nc_decode_stream": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P]),
     "nc_get_stats": (C.c_int, [_P, C.POINTER(NcStats)]),
-    "nc_profile": (C.c_int, [_P, C.c_int32]),
+    "nc_profile": (C.c_int, [_P, C.c_int32, C.c_uint32]),
     "nc_autotune": (C.c_int, [_P, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint32,
                               C.POINTER(C.c_uint32)]),
     "nc_tiles_reset": (C.c_int, [_P]),

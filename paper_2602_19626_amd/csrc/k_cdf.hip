@@ -76,12 +76,12 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_scan_kernel(
 }
 
 // One workgroup per row for V <= 49,152 (768 threads; thread t owns entries 3072 q + 4 t .. + 3,
-// q < 16).  A first sweep reads the row, reduces the floor counts, the lowest-index argmax and
-// the validity, and keeps each lane's 4-entry count sums; one barrier round scans all sixteen
-// 3072-entry blocks at once (a wave scan per block, the wave totals exchanged through LDS); a
-// second sweep re-reads the row (now cached close by), recomputes the counts and stores each
-// lane's four CDF entries with the widest stores the row's alignment allows.  Every result is an
-// integer or a comparison, so it equals the two-kernel result.
+// q < 16).  The row is read once into registers (64 floats per thread).  From them the kernel
+// reduces the floor counts, the lowest-index argmax and the validity; one barrier round scans all
+// sixteen 3072-entry blocks at once (a wave scan per block, block and wave offsets by a two-level
+// scan of the wave totals in LDS); the CDF is then written from the registers with the widest
+// stores the row's alignment allows.  Every result is an integer or a comparison, so it equals the
+// two-kernel result.
 typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 constexpr int kRowThreads = 768;
@@ -110,13 +110,24 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
   __shared__ uint32_t s_bi[kRowWaves];
   __shared__ int s_bad[kRowWaves];
   __shared__ uint32_t s_wt[kRowWaves][kRowBlocks];
+  __shared__ uint32_t s_bt[kRowBlocks];
   __shared__ uint32_t s_off[kRowWaves][kRowBlocks];
+  // per (block, thread): the 4-entry count sum, then its exclusive prefix within the wave
+  __shared__ uint32_t s_cnt[kRowBlocks][kRowThreads];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t row = blockIdx.x;
   const float* p = probs + size_t(row) * V;
   const uint32_t m = total - V;
-  // sweep 1
-  uint32_t s4[kRowBlocks];
+  // the whole row in registers: every load is issued before the first use (V % 4 == 0, so a
+  // group of four is either whole or past the end)
+  float x[kRowBlocks][4];
+  const f4v* p4 = reinterpret_cast<const f4v*>(p) + tid;
+#pragma unroll
+  for (int q = 0; q < kRowBlocks; ++q) {
+    const f4v v = q * kRowBlock + 4 * tid < V ? p4[q * kRowThreads] : f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[q][i] = v[i];
+  }
   uint64_t sum = 0;
   float best = -1.f;
   uint32_t bi = 0xFFFFFFFFu;
@@ -124,20 +135,19 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
 #pragma unroll
   for (int q = 0; q < kRowBlocks; ++q) {
     const uint32_t i0 = q * kRowBlock + 4 * tid;
-    float x[4];
-    row_load4(p, i0, V, x);
-    s4[q] = 0;
+    uint32_t c4 = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (i0 + i < V) {
-        if (!(x[i] >= 0.f && x[i] <= 1.f)) bad = 1;
-        s4[q] += floor_count(x[i], m);
-        if (x[i] > best) {
-          best = x[i];
+        if (!(x[q][i] >= 0.f && x[q][i] <= 1.f)) bad = 1;
+        c4 += floor_count(x[q][i], m);
+        if (x[q][i] > best) {
+          best = x[q][i];
           bi = i0 + i;
         }
       }
-    sum += s4[q];
+    s_cnt[q][tid] = c4;
+    sum += c4;
   }
   sum = wave_sum_u64(sum);
   wave_argmax(best, bi);
@@ -168,28 +178,35 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
     if (!rq.status && int64_t(floor_count(bv, m)) + r < 1) rq.status = 1;
     rq.start = 0;
   }
-  // the residual belongs to the argmax entry (corrected_count); per-block wave scans
-  uint32_t excl[kRowBlocks];
+  // the residual belongs to the argmax entry (corrected_count); per-block wave scans, the
+  // lane-exclusive prefixes parked in LDS to keep registers for the row
 #pragma unroll
   for (int q = 0; q < kRowBlocks; ++q) {
     const uint32_t i0 = q * kRowBlock + 4 * tid;
-    if (rq.argmax >= i0 && rq.argmax < i0 + 4) s4[q] = uint32_t(int32_t(s4[q]) + rq.residual);
-    uint32_t incl = s4[q];
+    uint32_t c4 = s_cnt[q][tid];
+    if (rq.argmax >= i0 && rq.argmax < i0 + 4) c4 = uint32_t(int32_t(c4) + rq.residual);
+    uint32_t incl = c4;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t y = __shfl_up(incl, d, 64);
       if (lane >= d) incl += y;
     }
     if (lane == 63) s_wt[w][q] = incl;
-    excl[q] = incl - s4[q];
+    s_cnt[q][tid] = incl - c4;
   }
   __syncthreads();
-  // CDF value before wave k's part of block q: all earlier blocks, then earlier waves of block q
+  // block totals, then the CDF value before wave k's part of block q: the earlier blocks' totals
+  // plus the earlier waves of block q
+  if (tid < kRowBlocks) {
+    uint32_t t = 0;
+    for (int k = 0; k < kRowWaves; ++k) t += s_wt[k][tid];
+    s_bt[tid] = t;
+  }
+  __syncthreads();
   if (tid < kRowWaves * kRowBlocks) {
     const int k = tid / kRowBlocks, q = tid % kRowBlocks;
     uint32_t o = 0;
-    for (int qq = 0; qq < q; ++qq)
-      for (int kk = 0; kk < kRowWaves; ++kk) o += s_wt[kk][qq];
+    for (int qq = 0; qq < q; ++qq) o += s_bt[qq];
     for (int kk = 0; kk < k; ++kk) o += s_wt[kk][q];
     s_off[k][q] = o;
   }
@@ -199,19 +216,17 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
     out[0] = 0;
     if (status) status[row] = rq.status;
   }
-  // sweep 2: entries 3072 q + 4 t + i go to out[1 + 3072 q + 4 t + i]; every such group of four
-  // starts at the same word phase within the row
+  // entries 3072 q + 4 t + i go to out[1 + 3072 q + 4 t + i]; every such group of four starts at
+  // the same word phase within the row
   const uint32_t phase = uint32_t((reinterpret_cast<uintptr_t>(out + 1) >> 2) & 3);
 #pragma unroll
   for (int q = 0; q < kRowBlocks; ++q) {
     const uint32_t i0 = q * kRowBlock + 4 * tid;
     if (i0 >= V) continue;
-    float x[4];
-    row_load4(p, i0, V, x);
-    uint32_t r4[4], run = s_off[w][q] + excl[q];
+    uint32_t r4[4], run = s_off[w][q] + s_cnt[q][tid];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      run += i0 + i < V ? corrected_count(x[i], i0 + i, rq) : 0u;
+      run += i0 + i < V ? corrected_count(x[q][i], i0 + i, rq) : 0u;
       r4[i] = run;
     }
     uint32_t* dst = out + 1 + i0;

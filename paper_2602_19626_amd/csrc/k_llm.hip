@@ -14,6 +14,7 @@
 #include "llm_dev.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 // Prefill and decode must round every shared expression identically: no contraction.
 #pragma clang fp contract(off)
@@ -146,18 +147,23 @@ __device__ __forceinline__ float a_row_inv(const GemmArgs& a, int ar) {
 
 // ---- epilogue emitters ----
 
-__device__ __forceinline__ void emit_qkv_prec(const GemmArgs& a, int prec_att, int m, int n,
-                                              float v, float partner) {
+// RoPE table entry (cos, sin) used by column n of a q/k head at position pos
+__device__ __forceinline__ float2 rope_cs(const GemmArgs& a, int pos, int n) {
+  const int h2 = a.hd / 2, within = n % a.hd;
+  const int i = within < h2 ? within : within - h2;
+  return *reinterpret_cast<const float2*>(a.rope + ((long long)pos * h2 + i) * 2);
+}
+
+// q/k/v output (m, n) = v (partner: the RoPE partner column's value) with the row's metadata rm
+// and, for q/k columns, its RoPE entry cs = rope_cs(a, rm.pos, n)
+__device__ __forceinline__ void emit_qkv_core(const GemmArgs& a, int prec_att, int m, int n,
+                                              float v, float partner, const RowMeta& rm,
+                                              float2 cs) {
   const int hd = a.hd, h2 = hd / 2;
   const int nq = a.Hq * hd, nk = a.Hk * hd;
-  const RowMeta rm = a.rows[m];
   const int within = n % hd;
-  if (n < nq + nk) {  // rotate-half RoPE on q and k
-    const int i = within < h2 ? within : within - h2;
-    const float cs = a.rope[((long long)rm.pos * h2 + i) * 2 + 0];
-    const float sn = a.rope[((long long)rm.pos * h2 + i) * 2 + 1];
-    v = within < h2 ? v * cs - partner * sn : v * cs + partner * sn;
-  }
+  if (n < nq + nk)  // rotate-half RoPE on q and k
+    v = within < h2 ? v * cs.x - partner * cs.y : v * cs.x + partner * cs.y;
   long long idx;
   void* base;
   if (n < nq) {
@@ -182,29 +188,32 @@ __device__ __forceinline__ void emit_qkv_prec(const GemmArgs& a, int prec_att, i
     PT<P_BF16>::store(base, idx, v, 1.f);
 }
 
+__device__ __forceinline__ void emit_qkv_prec(const GemmArgs& a, int prec_att, int m, int n,
+                                              float v, float partner) {
+  const RowMeta rm = a.rows[m];
+  const float2 cs = n < (a.Hq + a.Hk) * a.hd ? rope_cs(a, rm.pos, n) : float2{1.f, 0.f};
+  emit_qkv_core(a, prec_att, m, n, v, partner, rm, cs);
+}
+
 // emit_qkv_prec for rows m .. m + 3 of one column (BF16 attention operands), element for element
-// the same arithmetic; V^T gets one 8-byte store when the rows are 4 consecutive ring slots of
-// one stream.
-__device__ __forceinline__ void emit_qkv4_bf16(const GemmArgs& a, int m, int n, const float (&v)[4],
-                                               const float (&partner)[4]) {
+// the same arithmetic, with the rows' metadata rm and RoPE table rows rr (cos, sin pairs of
+// position rm[e].pos, in global memory or LDS) supplied by the caller; V^T gets one 8-byte store
+// when the rows are 4 consecutive ring slots of one stream.
+__device__ __forceinline__ void emit_qkv4_rows(const GemmArgs& a, int n, const RowMeta (&rm)[4],
+                                               const bool (&ok)[4], const float* const (&rr)[4],
+                                               const float (&v)[4], const float (&partner)[4],
+                                               int m) {
   const int hd = a.hd, h2 = hd / 2;
   const int nq = a.Hq * hd, nk = a.Hk * hd;
   const int within = n % hd;
-  RowMeta rm[4];
-  bool ok[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    ok[e] = m + e < a.M;
-    rm[e] = ok[e] ? a.rows[m + e] : RowMeta{0, 0, 0, 0};
-  }
   uint16_t h[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     float x = v[e];
-    if (n < nq + nk) {
+    if (n < nq + nk && ok[e]) {
       const int i = within < h2 ? within : within - h2;
-      const float cs = a.rope[((long long)rm[e].pos * h2 + i) * 2 + 0];
-      const float sn = a.rope[((long long)rm[e].pos * h2 + i) * 2 + 1];
+      const float cs = rr[e][i * 2 + 0];
+      const float sn = rr[e][i * 2 + 1];
       x = within < h2 ? x * cs - partner[e] * sn : x * cs + partner[e] * sn;
     }
     h[e] = f2bf(x);
@@ -348,6 +357,17 @@ struct Frag<P_FP8> {
 // next normed GEMM's operand quantise(xn * y_gain[n]).  Every lane of the wave must call this;
 // lanes with ok == false pass xn = 0 and store nothing.  Returns |xn * y_gain[n]|.
 template <int P>
+__device__ __forceinline__ float resid_out_g(const GemmArgs& a, int m, int n, float xn, int c,
+                                             bool ok, float gain) {
+  const float sq = block_ssq16(xn);
+  if (!ok) return 0.f;
+  if (a.ssq_out && c == 0) a.ssq_out[(long long)m * (a.N / 16) + n / 16] = sq;
+  if (!a.y_out) return 0.f;
+  const float yv = xn * gain;
+  PT<P>::store(a.y_out, (long long)m * a.N + n, yv, a.y_inv_scale);
+  return fabsf(yv);
+}
+template <int P>
 __device__ __forceinline__ float resid_out(const GemmArgs& a, int m, int n, float xn, int c,
                                            bool ok) {
   const float sq = block_ssq16(xn);
@@ -444,6 +464,25 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
   };
 
   if constexpr (EPI == E_STORE || EPI == E_RESID) {
+    // residual values and gains are loaded before the first store (see the wide kernel)
+    float xo[RB][CB][4], gn[CB];
+    if constexpr (EPI == E_RESID) {
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int n = n0 + wn * WN + j * 16 + fr;
+        gn[j] = (a.y_out && n < a.N) ? a.y_gain[n] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int m = m0 + wm * WM + i * 16 + fg * 4 + e;
+            const int n = n0 + wn * WN + j * 16 + fr;
+            xo[i][j][e] = (m < a.M && n < a.N) ? a.out_f32[(long long)m * a.ldo + n] : 0.f;
+          }
+    }
     float ymax = 0.f;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -457,11 +496,10 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(const Gemm
           if constexpr (EPI == E_RESID) {
             float xn = 0.f;
             if (ok) {
-              float* o = a.out_f32 + (long long)m * a.ldo + n;
-              xn = *o + val(i, j, e);
-              *o = xn;
+              xn = xo[i][j][e] + val(i, j, e);
+              a.out_f32[(long long)m * a.ldo + n] = xn;
             }
-            ymax = fmaxf(ymax, resid_out<P>(a, m, n, xn, fr, ok));
+            ymax = fmaxf(ymax, resid_out_g<P>(a, m, n, xn, fr, ok, gn[j]));
           } else if (ok) {
             a.out_f32[(long long)m * a.ldo + n] = val(i, j, e);
           }
@@ -546,20 +584,29 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
   for (int r = tid; r < WBM; r += WTHREADS)
     s_inv[r] = (AM == A_NORM && s_arow[r] >= 0) ? a_row_inv(a, s_arow[r]) : 1.f;
 
-  // global -> register staging of one K part
+  // global -> register staging of one K part; each thread's row addresses are resolved once
   v4i ra[NB16], rb[NB16];
-  const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
-  const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
+  const uint8_t* pa[NB16];
+  const uint8_t* pw[NB16];
+  int kc16[NB16];
+  {
+    const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
+    const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
+#pragma unroll
+    for (int u = 0; u < NB16; ++u) {
+      const int c = tid + u * WTHREADS, r = c / CPR;
+      kc16[u] = (c % CPR) * (16 / ES);
+      const int ar = s_arow[r], n = n0 + r;
+      pa[u] = ar >= 0 ? A8 + ((long long)ar * K + kc16[u]) * ES : nullptr;
+      pw[u] = n < a.N ? W8 + ((long long)n * K + kc16[u]) * ES : nullptr;
+    }
+  }
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NB16; ++u) {
-      const int c = tid + u * WTHREADS, r = c / CPR, k = k0 + (c % CPR) * (16 / ES);
-      const int ar = s_arow[r];
-      ra[u] = (ar >= 0 && k < K) ? *reinterpret_cast<const v4i*>(A8 + ((long long)ar * K + k) * ES)
-                                 : v4i{0, 0, 0, 0};
-      const int n = n0 + r;
-      rb[u] = (n < a.N && k < K) ? *reinterpret_cast<const v4i*>(W8 + ((long long)n * K + k) * ES)
-                                 : v4i{0, 0, 0, 0};
+      const bool kin = k0 + kc16[u] < K;
+      ra[u] = (pa[u] && kin) ? *reinterpret_cast<const v4i*>(pa[u] + k0 * ES) : v4i{0, 0, 0, 0};
+      rb[u] = (pw[u] && kin) ? *reinterpret_cast<const v4i*>(pw[u] + k0 * ES) : v4i{0, 0, 0, 0};
     }
   };
   auto stage = [&](uint8_t* buf) {
@@ -607,7 +654,26 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
   auto val = [&](int i, int j, int e) {
     return tot[i][j][e] * deq * s_inv[wm * 64 + i * 16 + fg * 4 + e];
   };
-  if constexpr (EPI == E_STORE || EPI == E_RESID) {
+  if constexpr (EPI == E_RESID) {
+    // every residual value and gain of the lane is loaded before the first store, so the loads
+    // overlap instead of each waiting behind the previous output's store
+    float xo[4][4][4], gn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = nw + j * 16 + fr;
+      gn[j] = (a.y_out && n < a.N) ? a.y_gain[n] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = mw + i * 16 + fg * 4 + e;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = nw + j * 16 + fr;
+          xo[i][j][e] = (m < a.M && n < a.N) ? a.out_f32[(long long)m * a.ldo + n] : 0.f;
+        }
+      }
     float ymax = 0.f;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -618,20 +684,27 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
         for (int j = 0; j < 4; ++j) {
           const int n = nw + j * 16 + fr;
           const bool ok = m < a.M && n < a.N;
-          if constexpr (EPI == E_RESID) {
-            float xn = 0.f;
-            if (ok) {
-              float* o = a.out_f32 + (long long)m * a.ldo + n;
-              xn = *o + val(i, j, e);
-              *o = xn;
-            }
-            ymax = fmaxf(ymax, resid_out<P>(a, m, n, xn, fr, ok));
-          } else if (ok) {
-            a.out_f32[(long long)m * a.ldo + n] = val(i, j, e);
+          float xn = 0.f;
+          if (ok) {
+            xn = xo[i][j][e] + val(i, j, e);
+            a.out_f32[(long long)m * a.ldo + n] = xn;
           }
+          ymax = fmaxf(ymax, resid_out_g<P>(a, m, n, xn, fr, ok, gn[j]));
         }
       }
-    if constexpr (EPI == E_RESID) amax_flush(a.y_amax, ymax, lane);
+    amax_flush(a.y_amax, ymax, lane);
+  } else if constexpr (EPI == E_STORE) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = mw + i * 16 + fg * 4 + e;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = nw + j * 16 + fr;
+          if (m < a.M && n < a.N) a.out_f32[(long long)m * a.ldo + n] = val(i, j, e);
+        }
+      }
   } else if constexpr (EPI == E_GLU) {
     float omax = 0.f;
 #pragma unroll
@@ -648,25 +721,65 @@ __global__ __launch_bounds__(WTHREADS, 2) void gemm_wide_kernel(const GemmArgs a
       }
     amax_flush(a.out_amax, omax, lane);
   } else if constexpr (EPI == E_QKV) {
+    // the staging LDS is free after the last part's barrier: stage the tile rows' metadata and,
+    // when the tile holds q/k columns, their RoPE table rows, so that the epilogue issues no
+    // dependent global loads
     const int nqk = (a.Hq + a.Hk) * a.hd;
     const int px = a.hd == 64 ? 2 : 1;
+    const int h2 = a.hd / 2;
+    RowMeta* s_rm = reinterpret_cast<RowMeta*>(lds);
+    float* s_rope = reinterpret_cast<float*>(lds + WBM * sizeof(RowMeta));
+    const bool rope = n0 < nqk;
+    for (int r = tid; r < WBM; r += WTHREADS)
+      s_rm[r] = m0 + r < a.M ? a.rows[m0 + r] : RowMeta{0, 0, 0, 0};
+    __syncthreads();
+    if (rope) {
+      for (int t = tid; t < WBM * h2; t += WTHREADS) {
+        const int r = t / h2, i = t % h2;
+        if (m0 + r < a.M) {
+          const float2 cs = *reinterpret_cast<const float2*>(a.rope +
+                                                            ((long long)s_rm[r].pos * h2 + i) * 2);
+          *reinterpret_cast<float2*>(s_rope + (r * h2 + i) * 2) = cs;
+        }
+      }
+      __syncthreads();
+    }
+    // the partner block j ^ px must be a compile-time index, or the accumulators would be
+    // addressed dynamically and leave the registers
+    auto emit_all = [&](auto pxc) {
+      constexpr int PX = decltype(pxc)::value;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = mw + i * 16 + fg * 4;
-      if (m >= a.M) continue;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = nw + j * 16 + fr;
-        if (n >= a.N) continue;
-        float v[4], pr[4];
+      for (int i = 0; i < 4; ++i) {
+        const int rl = wm * 64 + i * 16 + fg * 4;  // tile row of e = 0
+        const int m = m0 + rl;
+        if (m >= a.M) continue;
+        RowMeta rm[4];
+        bool ok[4];
+        const float* rr[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          v[e] = val(i, j, e);
-          pr[e] = n < nqk ? val(i, j ^ px, e) : 0.f;
+          ok[e] = m + e < a.M;
+          rm[e] = s_rm[rl + e];
+          rr[e] = s_rope + (rl + e) * h2 * 2;
         }
-        emit_qkv4_bf16(a, m, n, v, pr);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = nw + j * 16 + fr;
+          if (n >= a.N) continue;
+          float v[4], pr[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            v[e] = val(i, j, e);
+            pr[e] = n < nqk ? val(i, j ^ PX, e) : 0.f;
+          }
+          emit_qkv4_rows(a, n, rm, ok, rr, v, pr, m);
+        }
       }
-    }
+    };
+    if (px == 2)
+      emit_all(std::integral_constant<int, 2>{});
+    else
+      emit_all(std::integral_constant<int, 1>{});
   }
 }
 
@@ -689,6 +802,8 @@ static void gemm_wide(const GemmArgs& a, hipStream_t s) {
 
 constexpr int SPLIT_WAVES = 16;
 constexpr int SPLIT_ROWS = 64;
+constexpr int kSsqPre = 4;    // staged block sums of squares held per thread during the parts
+constexpr int kSsqStage = 64;  // staged only for K <= 16 * kSsqStage
 constexpr int SKINNY_ROWS = 256;  // below this many rows the split kernel is used
 
 // inv[a_rows[m]] = the RMSNorm scale of row a_rows[m] (for the output layer)
@@ -729,8 +844,45 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   const int M = min(a.M - r0, MB * 16);
   const int gs = group_size(EPI, a.hd);
   float* s_inv = lds + S * gs * MB * 256;
+  float* s_ssq = s_inv + SPLIT_ROWS;  // [row][K / 16] when staged
   const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
   const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
+  // Row scales of a normed GEMM: their inputs (the block sums of squares, or the given scales)
+  // are loaded before the parts' operands, so that their latency overlaps the parts' loads
+  // instead of following the last MFMA.
+  const int nb16 = K / 16;
+  const int nss = (AM == A_NORM && !a.inv) ? M * nb16 : 0;
+  const bool staged = nss > 0 && nb16 <= kSsqStage && nss <= kSsqPre * int(blockDim.x);
+  float pre[kSsqPre];
+  float pre_inv = 1.f;
+  if (staged) {
+#pragma unroll
+    for (int k = 0; k < kSsqPre; ++k) {
+      const int i = threadIdx.x + k * int(blockDim.x);
+      if (i < nss) {
+        const int m = i / nb16;
+        const int ar = a.a_rows ? a.a_rows[r0 + m] : r0 + m;
+        pre[k] = a.ssq[(long long)ar * nb16 + (i - m * nb16)];
+      }
+    }
+  } else if (AM == A_NORM && a.inv && int(threadIdx.x) < M) {
+    pre_inv = a.inv[a.a_rows ? a.a_rows[r0 + threadIdx.x] : r0 + threadIdx.x];
+  }
+  // The inputs of this thread's first epilogue item are fetched now as well: the row metadata of
+  // a q/k/v output (its RoPE entry follows once the metadata is in), or the residual value and
+  // gain of a residual output.
+  RowMeta pre_rm{0, 0, 0, 0};
+  float2 pre_cs{1.f, 0.f};
+  float pre_x = 0.f, pre_g = 0.f;
+  if constexpr (EPI == E_QKV) {
+    if (int(threadIdx.x) < M * gs * 16) pre_rm = a.rows[r0 + threadIdx.x / (gs * 16)];
+  } else if constexpr (EPI == E_RESID) {
+    const int t = threadIdx.x, n = gi * 16 + (t & 15);
+    if (t < M * 16 && n < N) {
+      pre_x = a.out_f32[(long long)(r0 + (t >> 4)) * a.ldo + n];
+      if (a.y_out) pre_g = a.y_gain[n];
+    }
+  }
   // residual GEMMs include the long-K down projection, whose waves own two parts: there the
   // second part's loads go out with the first's (a second register buffer)
   constexpr int NBUF = EPI == E_RESID ? 2 : 1;
@@ -784,8 +936,28 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       compute_part(s, 0);
     }
   }
-  for (int m = threadIdx.x; m < M; m += blockDim.x)
-    s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
+  if constexpr (EPI == E_QKV) {
+    const int t = threadIdx.x;
+    const int n = group_block(EPI, a.hd, gi, (t >> 4) % gs) * 16 + (t & 15);
+    if (t < M * gs * 16 && n < (a.Hq + a.Hk) * a.hd) pre_cs = rope_cs(a, pre_rm.pos, n);
+  }
+  if (staged) {
+#pragma unroll
+    for (int k = 0; k < kSsqPre; ++k) {
+      const int i = threadIdx.x + k * int(blockDim.x);
+      if (i < nss) s_ssq[i] = pre[k];
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += blockDim.x)
+      s_inv[m] = inv_from_ssq(s_ssq + m * nb16, K, a.eps);
+  } else if (AM == A_NORM && a.inv) {
+    if (int(threadIdx.x) < M) s_inv[threadIdx.x] = pre_inv;
+    for (int m = threadIdx.x + blockDim.x; m < M; m += blockDim.x)
+      s_inv[m] = a.inv[a.a_rows ? a.a_rows[r0 + m] : r0 + m];
+  } else {
+    for (int m = threadIdx.x; m < M; m += blockDim.x)
+      s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
+  }
   __syncthreads();
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
   // output (row m of the chunk, block j, column c) = (partials summed in part order) * deq * scale
@@ -812,12 +984,13 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       const int n = gi * 16 + c;
       const bool ok = t < M * 16 && n < N;
       float xn = 0.f;
+      float* o = a.out_f32 + (long long)(r0 + m) * a.ldo + n;
       if (ok) {
-        float* o = a.out_f32 + (long long)(r0 + m) * a.ldo + n;
-        xn = *o + sum(m, 0, c);
+        xn = (t0 == 0 ? pre_x : *o) + sum(m, 0, c);
         *o = xn;
       }
-      ymax = fmaxf(ymax, resid_out<P>(a, r0 + m, n, xn, c, ok));
+      const float g = t0 == 0 ? pre_g : (ok && a.y_out ? a.y_gain[n] : 0.f);
+      ymax = fmaxf(ymax, resid_out_g<P>(a, r0 + m, n, xn, c, ok, g));
     }
     amax_flush(a.y_amax, ymax, lane);
   } else {
@@ -826,6 +999,7 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       const int m = t / (gs * 16), j = (t >> 4) % gs, c = t & 15;
       const int n = group_block(EPI, a.hd, gi, j) * 16 + c;
       if (n >= N) continue;
+      const bool first = t == int(threadIdx.x);
       const float v = sum(m, j, c);
       const long long row = r0 + m;
       if constexpr (EPI == E_STORE) {
@@ -833,7 +1007,10 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       } else {
         float partner = 0.f;
         if (n < nqk) partner = a.hd == 16 ? sum(m, 0, c ^ 8) : sum(m, 1 - j, c);
-        emit_qkv_prec(a, P == P_F32 ? P_F32 : P_BF16, int(row), n, v, partner);
+        if (first)
+          emit_qkv_core(a, P == P_F32 ? P_F32 : P_BF16, int(row), n, v, partner, pre_rm, pre_cs);
+        else
+          emit_qkv_prec(a, P == P_F32 ? P_F32 : P_BF16, int(row), n, v, partner);
       }
     }
   }
@@ -1311,7 +1488,10 @@ static int split_mb(const GemmArgs& a, int epi) {
 static int split_parts(const GemmArgs& a) { return (a.K + KP - 1) / KP; }
 
 static size_t split_lds(const GemmArgs& a, int epi, int mb) {
-  return (size_t(split_parts(a)) * group_size(epi, a.hd) * mb * 256 + SPLIT_ROWS) * sizeof(float);
+  const int nb16 = a.K / 16;
+  const size_t ssq = (epi != E_RESID && nb16 <= kSsqStage) ? size_t(mb) * 16 * nb16 : 0;
+  return (size_t(split_parts(a)) * group_size(epi, a.hd) * mb * 256 + SPLIT_ROWS + ssq) *
+         sizeof(float);
 }
 
 template <int P, int AM, int EPI>

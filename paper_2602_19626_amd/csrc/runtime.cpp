@@ -129,6 +129,9 @@ struct nc_ctx {
   VocabParams vp{};
   // measurement: events around launches of one kernel class
   int prof_class = -1;
+  uint32_t prof_stride = 1;   // time every prof_stride-th launch of the class
+  uint64_t prof_seen = 0;     // launches of the class since nc_profile
+  bool prof_open = false;     // the current launch is being timed
   nc_kstat prof{};
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_busy;
@@ -228,15 +231,20 @@ void sync(nc_ctx* c) {
 // Bracket the launches of one kernel class; bytes / flops are the launch's algorithmic work.
 void prof_begin(nc_ctx* c, int cls) {
   if (cls != c->prof_class) return;
+  c->prof_open = c->prof_seen++ % c->prof_stride == 0;
+  if (!c->prof_open) return;
   c->ev_open = take_event(c);
   NC_HIP(hipEventRecord(c->ev_open, c->st));
 }
 void prof_end(nc_ctx* c, int cls, double bytes, double flops) {
   if (cls != c->prof_class) return;
+  c->prof.launches += 1;
+  if (!c->prof_open) return;
+  c->prof_open = false;
   hipEvent_t e = take_event(c);
   NC_HIP(hipEventRecord(e, c->st));
   c->ev_busy.emplace_back(c->ev_open, e);
-  c->prof.launches += 1;
+  c->prof.timed += 1;
   c->prof.bytes += bytes;
   c->prof.flops += flops;
   if (c->ev_busy.size() > 4096) sync(c);
@@ -1336,13 +1344,17 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
   });
 }
 
-nc_status nc_profile(nc_ctx* c, int32_t cls) {
+nc_status nc_profile(nc_ctx* c, int32_t cls, uint32_t stride) {
   return guard([&] {
     NC_CHECK(c, NC_E_INVALID, "NULL context");
     NC_CHECK(cls >= -1 && cls < NC_K_COUNT, NC_E_INVALID, "bad kernel class");
+    NC_CHECK(stride >= 1, NC_E_INVALID, "stride must be >= 1");
     NC_HIP(hipSetDevice(c->dev));
     sync(c);
     c->prof_class = cls;
+    c->prof_stride = stride;
+    c->prof_seen = 0;
+    c->prof_open = false;
     c->prof = nc_kstat{};
   });
 }
@@ -1374,16 +1386,24 @@ nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out,
     NC_HIP(hipMemsetAsync(c->xinv.p, 0, c->xinv.n * sizeof(float), c->st));
     NC_HIP(hipMemsetAsync(c->hb.p, 0, c->hb.n, c->st));
     NC_HIP(hipMemsetAsync(c->ob.p, 0, c->ob.n, c->st));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    NC_HIP(hipEventCreate(&e0));
-    NC_HIP(hipEventCreate(&e1));
-    struct Ev {
-      hipEvent_t a, b;
-      ~Ev() {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+    struct Events {
+      std::vector<hipEvent_t> e;
+      hipEvent_t operator[](size_t i) const { return e[i]; }
+      ~Events() {
+        for (hipEvent_t x : e) (void)hipEventDestroy(x);
       }
-    } ev{e0, e1};
+    } ev;
+    for (uint32_t i = 0; i < 2 * reps; ++i) {
+      hipEvent_t x = nullptr;
+      NC_HIP(hipEventCreate(&x));
+      ev.e.push_back(x);
+    }
+    struct Scratch {
+      DevBuf<uint8_t> b;
+      ~Scratch() { b.release(); }
+    } fl;  // released when the tuner returns, also on an error
+    fl.b.alloc(size_t(512) << 20);
+    DevBuf<uint8_t>& flush = fl.b;
     const int prec = c->prec;
     uint32_t n = 0;
     for (int g = 0; g < NC_G_COUNT; ++g) {
@@ -1397,23 +1417,37 @@ nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out,
           continue;
         }
         const int M = std::min(kRowBucketHi[b], top);
-        GemmArgs a;
-        switch (g) {
-          case NC_G_QKV: a = args_qkv(c, 0, M, c->rowsd.p, false); break;
-          case NC_G_OPROJ: a = args_oproj(c, 0, M, false, nullptr); break;
-          case NC_G_GATEUP: a = args_gateup(c, 0, M, false, nullptr); break;
-          case NC_G_DOWN: a = args_down(c, 0, M, false); break;
-          default: a = args_lm(c, c->yb.p, c->xinv.p, nullptr, M, c->z.p, false); break;
+        // the GEMM of every layer in turn, as a pass meets them: weights come from HBM, not
+        // from a cache warmed by the previous repetition
+        std::vector<GemmArgs> la(g == NC_G_LMHEAD ? 1 : c->nl);
+        for (int l = 0; l < int(la.size()); ++l) {
+          switch (g) {
+            case NC_G_QKV: la[l] = args_qkv(c, l, M, c->rowsd.p, false); break;
+            case NC_G_OPROJ: la[l] = args_oproj(c, l, M, false, nullptr); break;
+            case NC_G_GATEUP: la[l] = args_gateup(c, l, M, false, nullptr); break;
+            case NC_G_DOWN: la[l] = args_down(c, l, M, false); break;
+            default: la[l] = args_lm(c, c->yb.p, c->xinv.p, nullptr, M, c->z.p, false); break;
+          }
         }
+        const GemmArgs& a = la[0];
+        // each timed launch follows a write over twice the last-level cache, as in a pass, where
+        // the KV-cache stream between two uses of a layer's weights evicts them
         auto time_us = [&](const GemmTile& t) {
-          for (int w = 0; w < 2; ++w) launch_gemm(prec, kAm[g], kEpi[g], a, c->st, t);
-          NC_HIP(hipEventRecord(e0, c->st));
-          for (uint32_t r = 0; r < reps; ++r) launch_gemm(prec, kAm[g], kEpi[g], a, c->st, t);
-          NC_HIP(hipEventRecord(e1, c->st));
-          NC_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          NC_HIP(hipEventElapsedTime(&ms, e0, e1));
-          return 1000.f * ms / float(reps);
+          launch_gemm(prec, kAm[g], kEpi[g], a, c->st, t);
+          for (uint32_t r = 0; r < reps; ++r) {
+            NC_HIP(hipMemsetAsync(flush.p, int(r & 0xFF), flush.n, c->st));
+            NC_HIP(hipEventRecord(ev[2 * r], c->st));
+            launch_gemm(prec, kAm[g], kEpi[g], la[r % la.size()], c->st, t);
+            NC_HIP(hipEventRecord(ev[2 * r + 1], c->st));
+          }
+          NC_HIP(hipEventSynchronize(ev[2 * reps - 1]));
+          float tot = 0.f;
+          for (uint32_t r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            NC_HIP(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+            tot += ms;
+          }
+          return 1000.f * tot / float(reps);
         };
         const float us_default = time_us(GemmTile{});
         GemmTile best{};

@@ -15,7 +15,7 @@ def _chunks():
 
 def test_layout_matches_the_paper_byte_counts():
     ch = _chunks()
-    blob = ct.pack(ch, ct.F_NGRAM | ct.F_HEAD | ct.F_SKIP, tau=1.0)
+    blob = ct.pack(ch, ct.F_NGRAM | ct.F_HEAD | ct.F_SKIP, tau=1.0, checksum=False)
     # 9-byte header: magic, flags, tau, chunk count; then 12 bytes per chunk; then the payload
     assert blob[:4] == b"NC05"
     assert blob[4] == 7
@@ -36,13 +36,33 @@ def test_round_trip():
 
 @pytest.mark.parametrize("cut", [3, 8, 15, 40])
 def test_truncated_containers_are_rejected(cut):
-    blob = ct.pack(_chunks(), 0)
+    blob = ct.pack(_chunks(), 0, checksum=cut % 2 == 0)
     with pytest.raises(ValueError):
         ct.unpack(blob[:cut])
 
 
+def test_checksum_trailer_detects_corruption():
+    import zlib
+    ch = _chunks()
+    plain = ct.pack(ch, ct.F_HEAD, checksum=False)
+    blob = ct.pack(ch, ct.F_HEAD)
+    # the same bytes with flags bit 7 set, plus the CRC-32 of everything before the trailer
+    assert len(blob) == len(plain) + 4 and blob[4] == ct.F_HEAD | ct.F_CRC
+    assert blob[:4] == plain[:4] and blob[5:-4] == plain[5:]
+    assert struct.unpack("<I", blob[-4:])[0] == zlib.crc32(blob[:-4])
+    flags, _, back = ct.unpack(blob)
+    assert flags == ct.F_HEAD and [c.data for c in back] == [c.data for c in ch]
+    for pos in (0, 9, 30, len(blob) - 10, len(blob) - 1):
+        bad = bytearray(blob)
+        bad[pos] ^= 0x10
+        with pytest.raises(ValueError):
+            ct.unpack(bytes(bad))
+    with pytest.raises(ValueError):
+        ct.pack(ch, ct.F_CRC)
+
+
 def test_bad_magic_trailing_bytes_and_limits():
-    blob = ct.pack(_chunks(), 0)
+    blob = ct.pack(_chunks(), 0, checksum=False)
     with pytest.raises(ValueError):
         ct.unpack(b"NC06" + blob[4:])
     with pytest.raises(ValueError):
