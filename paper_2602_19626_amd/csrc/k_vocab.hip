@@ -29,10 +29,18 @@ __device__ __forceinline__ LsePart lse_merge(LsePart a, LsePart b) {
   return LsePart{M, a.s * expf(a.m - M) + b.s * expf(b.m - M)};
 }
 
-// logsumexp of the row from its segment partials, combined in segment order
+// logsumexp of the row from its segment partials, combined in segment order; the partials are
+// read 16 at a time before they are merged, so their loads overlap
 __device__ __forceinline__ float row_lse(const LsePart* parts, int nseg) {
-  LsePart acc = parts[0];
-  for (int k = 1; k < nseg; ++k) acc = lse_merge(acc, parts[k]);
+  LsePart acc{-INFINITY, 0.f};
+  for (int k0 = 0; k0 < nseg; k0 += 16) {
+    LsePart buf[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) buf[u] = k0 + u < nseg ? parts[k0 + u] : LsePart{-INFINITY, 0.f};
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (k0 + u < nseg) acc = k0 + u == 0 ? buf[u] : lse_merge(acc, buf[u]);
+  }
   return acc.m + logf(acc.s);
 }
 
@@ -45,10 +53,6 @@ struct RowIn {
   int mode, use_head, K, V;
   float w[kMaxExperts];
 };
-
-__device__ __forceinline__ float head_logit(const RowIn& R, int t) {
-  return R.use_head ? R.z[t] + R.b[t] : R.z[t];
-}
 
 // Coding probability of entry t from its logit z, bias b and n-gram probability g; *pt receives
 // the bias-head probability softmax(z + b)_t.
@@ -63,11 +67,6 @@ __device__ __forceinline__ float row_prob_v(const RowIn& R, int t, float z, floa
   float p = R.w[0] * q;
   for (int j = 1; j <= R.K; ++j) p = p + R.w[j] * R.pk[(size_t)(j - 1) * R.V + t];
   return p;
-}
-
-__device__ __forceinline__ float row_prob(const RowIn& R, int t, float* pt) {
-  return row_prob_v(R, t, R.mode != M_SKIP ? R.z[t] : 0.f, R.use_head && R.mode != M_SKIP ? R.b[t] : 0.f,
-                    R.mode != M_LLM ? R.png[t] : 0.f, pt);
 }
 
 // Mixture / gate weights of a stream: mixer w = exp(log w); ensemble w = softmax(theta).
@@ -166,32 +165,46 @@ __device__ __forceinline__ RowIn make_row(const VocabParams& P, const StreamStat
   return R;
 }
 
-// Probabilities of this thread's 16 entries of segment seg (4 contiguous per quarter, loaded as
-// vectors), zero at or beyond V.
-__device__ __forceinline__ void row_probs(const RowIn& R, uint32_t seg, int tid, float (&p)[4][4],
-                                          float (&pt)[4][4]) {
-  const bool llm = R.mode != M_SKIP, ng = R.mode != M_LLM, hb = R.use_head && llm;
+// This thread's 16 entries of segment seg (4 contiguous per quarter) of the row's logits, bias and
+// n-gram probabilities, loaded as vectors before the row's mode is known (the mode only selects
+// among them), so that these loads overlap the row-metadata loads.  V % 4 == 0: a group of four
+// is whole or past the end (zero).
+struct RowVec {
+  f4v z[4], b[4], g[4];
+};
+__device__ __forceinline__ void row_fetch(const VocabParams& P, const StreamState& S,
+                                          const StepArgs& A, int r, int s, uint32_t seg, int tid,
+                                          RowVec& v) {
+  const float* z = A.z + (size_t)r * P.V;
+  const float* b = S.b + (size_t)s * P.V;
+  const float* g = S.png + (size_t)s * P.V;
   const f4v zero4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const uint32_t t0 = seg_index(seg, j, tid, 0);
-    if (t0 + 3 < uint32_t(R.V)) {
-      const f4v zz = llm ? *reinterpret_cast<const f4v*>(R.z + t0) : zero4;
-      const f4v bb = hb ? *reinterpret_cast<const f4v*>(R.b + t0) : zero4;
-      const f4v gg = ng ? *reinterpret_cast<const f4v*>(R.png + t0) : zero4;
+    const bool in = t0 < uint32_t(P.V);
+    v.z[j] = in ? *reinterpret_cast<const f4v*>(z + t0) : zero4;
+    v.b[j] = in && P.use_head ? *reinterpret_cast<const f4v*>(b + t0) : zero4;
+    v.g[j] = in ? *reinterpret_cast<const f4v*>(g + t0) : zero4;
+  }
+}
+
+// Probabilities of this thread's 16 entries of segment seg from the fetched vectors, zero at or
+// beyond V.
+__device__ __forceinline__ void row_probs(const RowIn& R, const RowVec& v, uint32_t seg, int tid,
+                                          float (&p)[4][4], float (&pt)[4][4]) {
+  const bool llm = R.mode != M_SKIP, ng = R.mode != M_LLM, hb = R.use_head && llm;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) p[j][i] = row_prob_v(R, int(t0) + i, zz[i], bb[i], gg[i], &pt[j][i]);
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t t0 = seg_index(seg, j, tid, 0);
+    if (t0 < uint32_t(R.V)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        p[j][i] = row_prob_v(R, int(t0) + i, llm ? v.z[j][i] : 0.f, hb ? v.b[j][i] : 0.f,
+                             ng ? v.g[j][i] : 0.f, &pt[j][i]);
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t t = t0 + i;
-        if (t < uint32_t(R.V)) {
-          p[j][i] = row_prob(R, int(t), &pt[j][i]);
-        } else {
-          p[j][i] = 0.f;
-          pt[j][i] = 0.f;
-        }
-      }
+      for (int i = 0; i < 4; ++i) p[j][i] = pt[j][i] = 0.f;
     }
   }
 }
@@ -203,8 +216,11 @@ __device__ __forceinline__ void v2_seg(const VocabParams& P, const StreamState& 
   float p[4][4], pt[4][4];
   RowIn R;
   if (active) {
-    R = make_row(P, S, A, r, A.rows[r], nseg);
-    row_probs(R, seg, tid, p, pt);
+    const int s = A.rows[r];
+    RowVec v;
+    row_fetch(P, S, A, r, s, seg, tid, v);
+    R = make_row(P, S, A, r, s, nseg);
+    row_probs(R, v, seg, tid, p, pt);
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -229,8 +245,10 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
   RowIn R;
   float p[4][4], pt[4][4];
   if (active) {
+    RowVec v;
+    row_fetch(P, S, A, r, s, seg, tid, v);
     R = make_row(P, S, A, r, s, nseg);
-    row_probs(R, seg, tid, p, pt);
+    row_probs(R, v, seg, tid, p, pt);
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j)

@@ -78,3 +78,19 @@ def test_roundtrip_full_shape(oracle_run, prec):
     dec = ctx.decode_stream(together, [len(s) for s in streams])
     for a, b in zip(dec, streams):
         assert np.array_equal(a, b)
+
+
+def test_many_streams_batch_and_alone_agree_bf16(oracle_run):
+    """24 BF16 streams coded together (prefill passes of thousands of attention items, one wave
+    per item) and alone (a few hundred items per pass, a workgroup per quad plus the fold kernel)
+    give the same bytes, and the batch decodes back exactly."""
+    w, toks, orc = oracle_run
+    ctx, _ = make_context(WL, precision="bf16", max_streams=24)
+    streams = [synth.make_stream(150 + 7 * s, WL.shape.vocab, seed=300 + s, span=WL.span)
+               for s in range(24)]
+    together, _ = ctx.encode_stream(streams)
+    for s in (0, 11, 23):
+        assert together[s] == ctx.encode_stream([streams[s]])[0][0], s
+    dec = ctx.decode_stream(together, [len(s) for s in streams])
+    for a, b in zip(dec, streams):
+        assert np.array_equal(a, b)
