@@ -242,10 +242,15 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
   if (active && tid < nseg)
     L.parts[tid] = static_cast<const SegPartial*>(A.seg_parts)[(size_t)r * nseg + tid];
   if (tid == 0) *s_sym = -1;
+  // the key (decode: the host's target; encode: the token at the stream's next position) is
+  // fetched with the row, not after the scan
+  const int i_pos = active ? S.ncommit[s] : 0;
+  const uint32_t key =
+      !active ? 0u : (A.decode ? A.targets[r] : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
   RowIn R;
+  RowVec v;
   float p[4][4], pt[4][4];
   if (active) {
-    RowVec v;
     row_fetch(P, S, A, r, s, seg, tid, v);
     R = make_row(P, S, A, r, s, nseg);
     row_probs(R, v, seg, tid, p, pt);
@@ -260,9 +265,6 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
   if (active) q = seg_combine(L.parts, nseg, seg, V, P.total);
   uint32_t base[4];
   seg_scan(p, seg, V, q, base, L, tid);
-  const int i_pos = active ? S.ncommit[s] : 0;
-  const uint32_t key =
-      !active ? 0u : (A.decode ? A.targets[r] : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
   int found = -1;
   uint32_t fcl = 0, fch = 0;
   float fp = 0.f, fpt = 0.f;
@@ -331,16 +333,19 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
       !A.no_update) {
     const int sym = A.decode ? *s_sym : int(key);
     float* b = S.b + (size_t)s * V;
+    // b was fetched with the row (use_head) and only this workgroup writes these entries
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t0 = seg_index(seg, j, tid, 0);
+      if (t0 >= uint32_t(V)) continue;
+      f4v nb;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint32_t t = seg_index(seg, j, tid, i);
-        if (t < uint32_t(V)) {
-          const float ind = int(t) == sym ? 1.f : 0.f;
-          b[t] = b[t] - P.head_lr * (pt[j][i] - ind);
-        }
+        const float ind = int(t0) + i == sym ? 1.f : 0.f;
+        nb[i] = v.b[j][i] - P.head_lr * (pt[j][i] - ind);
       }
+      *reinterpret_cast<f4v*>(b + t0) = nb;
+    }
   }
   __syncthreads();  // L and s_sym are reused by the next call
 }
@@ -528,23 +533,35 @@ __device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& 
   const int s = rows[r];
   float h = 0.f, mx = 0.f;
   if (active) {
+    // unigram counts in, dense P_K out, four contiguous entries per load and store (V % 4 == 0)
+    typedef int32_t i4v __attribute__((ext_vector_type(4)));
+    i4v u[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t0 = seg_index(seg, j, tid, 0);
+      u[j] = t0 < uint32_t(V) ? *reinterpret_cast<const i4v*>(S.uni + (size_t)s * V + t0)
+                              : i4v{0, 0, 0, 0};
+    }
     const NgRow g = ng_row(P, S, s);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t0 = seg_index(seg, j, tid, 0);
+      if (t0 >= uint32_t(V)) continue;
+      f4v out;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint32_t t = seg_index(seg, j, tid, i);
-        if (t < uint32_t(V)) {
-          float pv = ng_base(S, g, s, V, int(t));
-          for (int k = 1; k <= P.K; ++k) {
-            if (g.present[k - 1]) pv = (1.0f - g.lam[k - 1]) * pv;
-            if (S.pk) S.pk[((size_t)s * P.K + (k - 1)) * V + t] = pv;
-          }
-          S.png[(size_t)s * V + t] = pv;
-          h = h - pv * log2f(pv);
-          mx = fmaxf(mx, pv);
+        const uint32_t t = t0 + i;
+        float pv = float(u[j][i] + 1) * g.inv_norm;  // ng_base
+        for (int k = 1; k <= P.K; ++k) {
+          if (g.present[k - 1]) pv = (1.0f - g.lam[k - 1]) * pv;
+          if (S.pk) S.pk[((size_t)s * P.K + (k - 1)) * V + t] = pv;
         }
+        out[i] = pv;
+        h = h - pv * log2f(pv);
+        mx = fmaxf(mx, pv);
       }
+      *reinterpret_cast<f4v*>(S.png + (size_t)s * V + t0) = out;
+    }
   }
   h = wave_sum_f(h);
   mx = wave_max_f(mx);
@@ -626,26 +643,33 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
       dh = dh + (old * log2f(old) - pv * log2f(pv));
       dmx = fmaxf(dmx, pv);
     }
-  if (active) {
-    F.sh[tid] = dh;
-    F.smx[tid] = dmx;
+  // sparse corrections: wave sums, then the four waves' in order; the dense segment partials are
+  // staged in LDS by as many threads, then added in segment order
+  dh = wave_sum_f(dh);
+  dmx = wave_max_f(dmx);
+  if (active && (tid & 63) == 0) {
+    F.sh[tid >> 6] = dh;
+    F.smx[tid >> 6] = dmx;
+  }
+  if (active && tid < nseg) {
+    const NgPart q = parts[(size_t)r * nseg + tid];
+    F.sh[kSegWaves + tid] = q.h;
+    F.smx[kSegWaves + tid] = q.mx;
   }
   __syncthreads();
-  for (int d = nt / 2; d > 0; d >>= 1) {
-    if (active && tid < d) {
-      F.sh[tid] = F.sh[tid] + F.sh[tid + d];
-      F.smx[tid] = fmaxf(F.smx[tid], F.smx[tid + d]);
-    }
-    __syncthreads();
-  }
   if (active && tid == 0) {
     float H = 0.f, mx = 0.f;
     for (int k = 0; k < nseg; ++k) {
-      H += parts[(size_t)r * nseg + k].h;
-      mx = fmaxf(mx, parts[(size_t)r * nseg + k].mx);
+      H += F.sh[kSegWaves + k];
+      mx = fmaxf(mx, F.smx[kSegWaves + k]);
     }
-    H = H + F.sh[0];
-    mx = fmaxf(mx, F.smx[0]);
+    float sh = F.sh[0], smx = F.smx[0];
+    for (int k = 1; k < kSegWaves; ++k) {
+      sh = sh + F.sh[k];
+      smx = fmaxf(smx, F.smx[k]);
+    }
+    H = H + sh;
+    mx = fmaxf(mx, smx);
     S.H[s] = H;
     S.pmax[s] = mx;
     const int pos = S.ncommit[s];
