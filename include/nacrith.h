@@ -225,7 +225,8 @@ nc_status nc_profile_read(nc_ctx* ctx, nc_kstat* out);
  * nc_autotune times, with HIP events on the library's stream, the fixed rule and every fitting
  * shape of each GEMM (QKV, O, gate/up, down, output layer) at the top of each row bucket
  * (1, 2, 4, 8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1024, ... rows) up to max_rows (the
- * output layer up to max_streams), `reps` launches per shape after one warm-up launch, each
+ * output layer up to the larger of max_streams and 2,048, its encode chunk), `reps` launches per
+ * shape after one warm-up launch, each
  * timed alone right after a 512 MiB device write that evicts the weights from the caches (as the
  * KV-cache stream of a pass does) and cycling through the layers' weights, and
  * keeps the fastest shape per (GEMM, bucket) for every later call on this context.  It writes

@@ -53,6 +53,9 @@ size_t prec_bytes(int p) { return p == P_F32 ? 4 : p == P_BF16 ? 2 : 1; }
 
 }  // namespace
 
+// Output-layer rows per encode chunk (logits 4 V bytes each: 400 MB at V = 49,152).
+constexpr int kEncodeHeadRows = 2048;
+
 // Row-count buckets of the launch-shape table: bucket i holds row counts in
 // (kRowBucketHi[i - 1], kRowBucketHi[i]].
 constexpr int kRowBuckets = 21;
@@ -110,6 +113,7 @@ struct nc_ctx {
   size_t spin_bytes = 0;
   // step buffers
   DevBuf<float> z;
+  DevBuf<float> zseg;  // encode: logits of a chunk of positions [pos][stream slot][V]
   DevBuf<int32_t> steprows, arows;
   DevBuf<uint32_t> targets;
   DevBuf<LsePart> lsep;
@@ -146,7 +150,7 @@ nc_ctx::~nc_ctx() {
   if (dev >= 0) (void)hipSetDevice(dev);
   if (st) (void)hipStreamSynchronize(st);
   for (void* p : allocs) (void)hipFree(p);
-  DevBuf<float>* fb[] = {&yb, &xss, &aws, &xinv, &hinv, &amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z,
+  DevBuf<float>* fb[] = {&yb, &xss, &aws, &xinv, &hinv, &amax, &rope, &b, &png, &pk, &lw, &Hd, &pmaxd, &hlast, &x, &ptok, &z, &zseg,
                          &dbgp, &dbgpt};
   for (auto* q : fb) q->release();
   DevBuf<int32_t>* ib[] = {&uni, &nseen, &hist, &ncommit, &moded, &next_ctx, &keys, &kidx,
@@ -1206,14 +1210,22 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
       const uint8_t* dst = upload_stage(c, stg);
       run_pass(c, plan, dst);
       const int32_t* seg_ar = reinterpret_cast<const int32_t*>(dst + off_ar);
-      for (size_t i = 0; i < seg_len; ++i) {
-        const int B = active[i];
-        run_lm_head(c, c->yb.p, c->xinv.p, seg_ar + i * n, B, c->z.p);
-        StepArgs A = step_args(c, B, false);
-        A.step_out = nullptr;
-        A.iv = c->iv.p;
-        A.ptok = c->ptok.p;
-        vocab_commit_step(c, A);
+      // The output layer depends only on the teacher-forced pass, not on the online models, so it
+      // runs once per chunk of positions (up to kEncodeHeadRows rows, one per (position, stream
+      // slot)); every position's vocabulary step then reads its B rows of the chunk.
+      const int pc = std::max(1, std::min(int(seg_len), kEncodeHeadRows / n));
+      c->zseg.alloc(size_t(pc) * n * c->V);
+      for (size_t i0 = 0; i0 < seg_len; i0 += pc) {
+        const int np = int(std::min(size_t(pc), seg_len - i0));
+        run_lm_head(c, c->yb.p, c->xinv.p, seg_ar + i0 * n, np * n, c->zseg.p);
+        for (size_t i = i0; i < i0 + np; ++i) {
+          StepArgs A = step_args(c, active[i], false);
+          A.z = c->zseg.p + (i - i0) * n * size_t(c->V);
+          A.step_out = nullptr;
+          A.iv = c->iv.p;
+          A.ptok = c->ptok.p;
+          vocab_commit_step(c, A);
+        }
       }
     }
     sync(c);
@@ -1372,9 +1384,11 @@ nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out,
     if (c->S_alloc < 1) reset_streams(c, 1, 1);
     const int Mmax = int(max_rows);
     // output-layer GEMMs only ever see one row per stream
-    const int Mlm = std::min(Mmax, c->cfg.max_streams);
+    // output-layer GEMMs see one row per stream (decode) or an encode chunk of positions
+    const int Mlm = std::min(Mmax, std::max(c->cfg.max_streams, kEncodeHeadRows));
     ensure_rows(c, Mmax);
-    ensure_step(c, Mlm);
+    ensure_step(c, std::min(Mmax, c->cfg.max_streams));
+    c->zseg.alloc(size_t(Mlm) * c->V);
     // scratch rows: stream 0, consecutive positions inside the RoPE table and the ring
     const int P = std::max(1, std::min(c->R, c->rope_pos));
     std::vector<RowMeta> rows(Mmax);
@@ -1426,7 +1440,7 @@ nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out,
             case NC_G_OPROJ: la[l] = args_oproj(c, l, M, false, nullptr); break;
             case NC_G_GATEUP: la[l] = args_gateup(c, l, M, false, nullptr); break;
             case NC_G_DOWN: la[l] = args_down(c, l, M, false); break;
-            default: la[l] = args_lm(c, c->yb.p, c->xinv.p, nullptr, M, c->z.p, false); break;
+            default: la[l] = args_lm(c, c->yb.p, c->xinv.p, nullptr, M, c->zseg.p, false); break;
           }
         }
         const GemmArgs& a = la[0];
