@@ -33,7 +33,9 @@ __device__ __forceinline__ uint32_t exact_floor_scaled(float p, uint32_t m) {
   const uint64_t mant = (bits & 0x7FFFFFu) | 0x800000u;  // p = mant * 2^(e - 150)
   const int sh = 150 - int(e);
   if (sh >= 64) return 0;
-  return uint32_t((mant * uint64_t(m)) >> sh);  // p <= 1 => sh >= 23, product < 2^48
+  // both factors are below 2^24 (the mask states it for m, which the callers' total <= 2^24
+  // bounds), so the product is two full-rate 24-bit multiplies rather than a 64-bit one
+  return uint32_t((mant * uint64_t(m & 0xFFFFFFu)) >> sh);  // p <= 1 => sh >= 23, < 2^48
 }
 
 __device__ __forceinline__ uint32_t floor_count(float p, uint32_t m) {
