@@ -338,8 +338,13 @@ def main():
         line["cpu_baseline"] = cb
         # gap of the GPU coder against the oracle's ideal code length, same prefix
         d, b = ctx.encode_stream([streams[0][:n_s]])
+        # against the oracle's ideal code length sum -log2 p (FP64, before quantisation); it can
+        # be negative: the one-count floor caps a near-zero probability's cost at log2 T bits
         line["gap_bits_per_token_sample"] = round((b[0] - ref.ideal_bits) / n_s, 5)
         line["gap_bpb_at_4_bytes_per_token"] = round(line["gap_bits_per_token_sample"] / 4.0, 5)
+        # against the oracle's own coder on its quantised CDFs, and its quantised ideal length
+        line["coded_bits_sample"] = {"gpu": int(b[0]), "oracle": int(ref.n_bits),
+                                     "oracle_quantised_ideal": round(ref.quant_bits, 3)}
     print(json.dumps(line), flush=True)
 
 
