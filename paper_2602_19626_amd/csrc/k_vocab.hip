@@ -499,24 +499,28 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
 struct NgRow {
   float lam[kMaxOrder];
   int present[kMaxOrder];
-  float inv_norm;  // 1 / (N + V)
+  int id[kMaxOrder];  // pool index of the order-k context of the next position, or -1
+  int n[kMaxOrder];   // its total count n_k
+  float inv_norm;     // 1 / (N + V)
 };
 
+// The row's n-gram weights: every order's context index is loaded first, then every count, so
+// the row costs two dependent loads rather than two per order.
 __device__ __forceinline__ NgRow ng_row(const VocabParams& P, const StreamState& S, int s) {
   NgRow g;
-  for (int k = 1; k <= kMaxOrder; ++k) {
-    g.present[k - 1] = 0;
-    g.lam[k - 1] = 0.f;
-    if (k > P.K) continue;
-    const int id = S.next_ctx[(size_t)s * kMaxOrder + (k - 1)];
-    if (id < 0) continue;
-    const size_t t = (size_t)s * P.K + (k - 1);
-    const int n = S.pool_sum[t * S.maxctx + id];
-    if (n <= 0) continue;
-    g.present[k - 1] = 1;
-    g.lam[k - 1] = float(n) / (float(n) + P.ngram_eps);
+#pragma unroll
+  for (int k = 0; k < kMaxOrder; ++k)
+    g.id[k] = k < P.K ? S.next_ctx[(size_t)s * kMaxOrder + k] : -1;
+  const int seen = S.nseen[s];
+#pragma unroll
+  for (int k = 0; k < kMaxOrder; ++k)
+    g.n[k] = g.id[k] >= 0 ? S.pool_sum[((size_t)s * P.K + k) * S.maxctx + g.id[k]] : 0;
+#pragma unroll
+  for (int k = 0; k < kMaxOrder; ++k) {
+    g.present[k] = g.n[k] > 0 ? 1 : 0;
+    g.lam[k] = g.present[k] ? float(g.n[k]) / (float(g.n[k]) + P.ngram_eps) : 0.f;
   }
-  g.inv_norm = 1.0f / float(S.nseen[s] + P.V);
+  g.inv_norm = 1.0f / float(seen + P.V);
   return g;
 }
 
@@ -601,14 +605,15 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
     for (int e = tid; e < P.K * kSlots; e += nt) {
       const int k = e / kSlots + 1, j = e % kSlots;
       if (!g.present[k - 1]) continue;
-      const int id = S.next_ctx[(size_t)s * kMaxOrder + (k - 1)];
+      const int id = g.id[k - 1];
       const size_t t = (size_t)s * P.K + (k - 1);
+      // the slot is read whether or not it is in use (readers stop at ln), so the slot and the
+      // slot count load together
+      const int2 tc = *reinterpret_cast<const int2*>(S.pool + ((t * S.maxctx + id) * kSlots + j) * 2);
       const int n = S.pool_n[t * S.maxctx + id];
       if (j == 0) F.ln[k - 1] = n;
-      if (j < n) {
-        F.lt[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 0];
-        F.lc[k - 1][j] = S.pool[((t * S.maxctx + id) * kSlots + j) * 2 + 1];
-      }
+      F.lt[k - 1][j] = tc.x;
+      F.lc[k - 1][j] = tc.y;
     }
   __syncthreads();
   float dh = 0.f, dmx = 0.f;
@@ -632,8 +637,7 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
           int cnt = 0;
           for (int j2 = 0; j2 < F.ln[k2 - 1]; ++j2)
             if (F.lt[k2 - 1][j2] == tok) cnt = F.lc[k2 - 1][j2];
-          const int id = S.next_ctx[(size_t)s * kMaxOrder + (k2 - 1)];
-          const float n = float(S.pool_sum[((size_t)s * P.K + (k2 - 1)) * S.maxctx + id]);
+          const float n = float(g.n[k2 - 1]);
           pv = g.lam[k2 - 1] * (float(cnt) / n) + (1.0f - g.lam[k2 - 1]) * pv;
         }
         if (S.pk) S.pk[((size_t)s * P.K + (k2 - 1)) * V + tok] = pv;
