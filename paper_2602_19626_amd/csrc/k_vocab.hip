@@ -244,7 +244,7 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
   if (tid == 0) *s_sym = -1;
   // the key (decode: the host's target; encode: the token at the stream's next position) is
   // fetched with the row, not after the scan
-  const int i_pos = active ? S.ncommit[s] : 0;
+  const int i_pos = !active ? 0 : (A.pos >= 0 ? A.pos : S.ncommit[s]);
   const uint32_t key =
       !active ? 0u : (A.decode ? A.targets[r] : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
   RowIn R;
@@ -411,18 +411,24 @@ __device__ int ctx_find(const StreamState& S, size_t t, const int32_t* toks, int
 __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& S,
                                        const StepArgs& A, int r, int k) {
   const int s = A.rows[r];
-  const Outcome o = A.out[r];
-  const bool on = k >= 0 && o.sym >= 0;
-  const int i = on ? S.ncommit[s] : 0;
   const int32_t* hist = S.hist + (size_t)s * S.maxT;
-  const int sym = o.sym;
+  // With the position given (batched encode) the committed token is the known one in hist, so the
+  // count updates need not wait for this step's outcome; the mixer update always reads it.
+  const bool given = A.pos >= 0 && !A.decode;
+  const bool counts = (A.upd & kUpdCounts) != 0, mixer = (A.upd & kUpdMixer) != 0;
+  const Outcome o = (mixer || !given) ? A.out[r] : Outcome{};
+  const int i = k < 0 ? 0 : (A.pos >= 0 ? A.pos : S.ncommit[s]);
+  const int sym = given ? hist[i] : o.sym;
+  const bool on = k >= 0 && sym >= 0 && (given || o.sym >= 0);
   __syncthreads();
-  if (on && k == 0) {
+  if (on && k == 0 && counts) {
     if (A.decode) S.hist[(size_t)s * S.maxT + i] = sym;
     if (P.use_ngram || P.ensemble) {
       S.uni[(size_t)s * P.V + sym] += 1;
       S.nseen[s] += 1;
     }
+  }
+  if (on && k == 0 && mixer && o.sym >= 0) {
     float* lw = S.lw + (size_t)s * kMaxExperts;
     if (o.mode == M_MIX) {
       // exponential weights (section 3.6): log w_j += eta log p_j(t*), then renormalise
@@ -438,7 +444,7 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
       for (int j = 0; j <= P.K; ++j) lw[j] = lw[j] - P.head_lr * (w[j] - o.r[j]);
     }
   }
-  if (on && (P.use_ngram || P.ensemble) && k >= 1 && k <= P.K) {
+  if (on && counts && (P.use_ngram || P.ensemble) && k >= 1 && k <= P.K) {
     const size_t t = (size_t)s * P.K + (k - 1);
     int32_t ctx[kMaxOrder];
     // insert t* as a continuation of the order-k context ending at t_{i-1}
@@ -491,7 +497,7 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
     S.next_ctx[(size_t)s * kMaxOrder + (k - 1)] = nid;
   }
   __syncthreads();
-  if (on && k == 0) S.ncommit[s] = i + 1;
+  if (on && k == 0 && counts) S.ncommit[s] = i + 1;
 }
 
 // ---- V6: dense n-gram prediction of the current position ------------------------------------
@@ -593,7 +599,7 @@ struct FixLds {
 __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& S,
                                        const int32_t* rows, const NgPart* parts, int nseg,
                                        StepOut* step_out, const Outcome* out, int r, int tid,
-                                       bool active, FixLds& F) {
+                                       bool active, FixLds& F, int pos_given) {
   const int nt = kSegThreads;
   const int V = P.V;
   const int s = rows[r];
@@ -676,7 +682,7 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
     mx = fmaxf(mx, smx);
     S.H[s] = H;
     S.pmax[s] = mx;
-    const int pos = S.ncommit[s];
+    const int pos = pos_given >= 0 ? pos_given : S.ncommit[s];
     int mode;
     if (P.ensemble) {
       mode = M_ENS;
@@ -745,9 +751,9 @@ __global__ __launch_bounds__(kSegThreads) void ngram_fix_kernel(VocabParams P, S
                                                                 const int32_t* rows,
                                                                 const NgPart* parts, int nseg,
                                                                 StepOut* step_out,
-                                                                const Outcome* out) {
+                                                                const Outcome* out, int pos) {
   __shared__ FixLds F;
-  v7_row(P, S, rows, parts, nseg, step_out, out, blockIdx.x, threadIdx.x, true, F);
+  v7_row(P, S, rows, parts, nseg, step_out, out, blockIdx.x, threadIdx.x, true, F, pos);
 }
 
 // ---- reset -----------------------------------------------------------------------------------
@@ -949,7 +955,7 @@ void launch_ensemble_backward(const float* z, float* b, float* theta, const floa
 
 // ---- launchers ------------------------------------------------------------------------------
 
-void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArgs& A,
+void launch_vocab_dist(const VocabParams& P, const StreamState& S, const StepArgs& A,
                        hipStream_t s) {
   if (A.B <= 0) return;
   const int nseg = int(ceil_div(P.V, kSeg));
@@ -957,22 +963,33 @@ void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArg
   hipLaunchKernelGGL(vocab_lse_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
   hipLaunchKernelGGL(vocab_count_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
   hipLaunchKernelGGL(vocab_scan_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
-  if (!A.no_update) {
-    if (P.ensemble)
-      hipLaunchKernelGGL(ensemble_bias_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
-    hipLaunchKernelGGL(ngram_update_kernel, dim3(A.B), dim3(64), 0, s, P, S, A);
-  }
+  if (!A.no_update && P.ensemble)
+    hipLaunchKernelGGL(ensemble_bias_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
   NC_HIP(hipGetLastError());
 }
 
+void launch_ngram_update(const VocabParams& P, const StreamState& S, const StepArgs& A,
+                         hipStream_t s) {
+  if (A.B <= 0 || A.no_update || !A.upd) return;
+  hipLaunchKernelGGL(ngram_update_kernel, dim3(A.B), dim3(64), 0, s, P, S, A);
+  NC_HIP(hipGetLastError());
+}
+
+void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArgs& A,
+                       hipStream_t s) {
+  launch_vocab_dist(P, S, A, s);
+  launch_ngram_update(P, S, A, s);
+}
+
 void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
-                          NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s) {
+                          NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s,
+                          int pos) {
   if (B <= 0) return;
   const int nseg = int(ceil_div(P.V, kSeg));
   hipLaunchKernelGGL(ngram_dense_kernel, dim3(nseg, B), dim3(kSegThreads), 0, s, P, S, rows,
                      parts);
   hipLaunchKernelGGL(ngram_fix_kernel, dim3(B), dim3(256), 0, s, P, S, rows, parts, nseg,
-                     step_out, out);
+                     step_out, out, pos);
   NC_HIP(hipGetLastError());
 }
 

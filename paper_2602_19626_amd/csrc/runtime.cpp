@@ -73,6 +73,10 @@ struct nc_ctx {
   int prec = P_F32, att = P_F32;
   int dev = 0;
   hipStream_t st = nullptr;
+  // batched encode: the n-gram update and prediction of the next position run on st2 beside the
+  // current position's distribution on st (events ev_dist[parity], ev_pred order them)
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_dist[2] = {nullptr, nullptr}, ev_pred = nullptr;
   int d = 0, hq = 0, hk = 0, hd = 0, F = 0, V = 0, nl = 0, R = 0;
   // weights
   std::vector<void*> allocs;
@@ -179,6 +183,9 @@ nc_ctx::~nc_ctx() {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
   }
+  for (hipEvent_t e : {ev_dist[0], ev_dist[1], ev_pred})
+    if (e) (void)hipEventDestroy(e);
+  if (st2) (void)hipStreamDestroy(st2);
   if (st) (void)hipStreamDestroy(st);
 }
 
@@ -227,26 +234,27 @@ void prof_flush(nc_ctx* c) {
 void sync(nc_ctx* c) {
   const auto t0 = std::chrono::steady_clock::now();
   NC_HIP(hipStreamSynchronize(c->st));
+  NC_HIP(hipStreamSynchronize(c->st2));
   c->stats.wait_seconds +=
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   prof_flush(c);
 }
 
 // Bracket the launches of one kernel class; bytes / flops are the launch's algorithmic work.
-void prof_begin(nc_ctx* c, int cls) {
+void prof_begin(nc_ctx* c, int cls, hipStream_t s = nullptr) {
   if (cls != c->prof_class) return;
   c->prof_open = c->prof_seen++ % c->prof_stride == 0;
   if (!c->prof_open) return;
   c->ev_open = take_event(c);
-  NC_HIP(hipEventRecord(c->ev_open, c->st));
+  NC_HIP(hipEventRecord(c->ev_open, s ? s : c->st));
 }
-void prof_end(nc_ctx* c, int cls, double bytes, double flops) {
+void prof_end(nc_ctx* c, int cls, double bytes, double flops, hipStream_t s = nullptr) {
   if (cls != c->prof_class) return;
   c->prof.launches += 1;
   if (!c->prof_open) return;
   c->prof_open = false;
   hipEvent_t e = take_event(c);
-  NC_HIP(hipEventRecord(e, c->st));
+  NC_HIP(hipEventRecord(e, s ? s : c->st));
   c->ev_busy.emplace_back(c->ev_open, e);
   c->prof.timed += 1;
   c->prof.bytes += bytes;
@@ -750,6 +758,15 @@ StreamState make_state(nc_ctx* c) {
   return S;
 }
 
+// The state with the n-gram distribution and mode of parity p (the pipelined encode alternates
+// them by position; every other path uses parity 0).
+StreamState state_par(nc_ctx* c, int p) {
+  StreamState S = c->S;
+  S.png = c->png.p + (size_t)p * c->S_alloc * c->V;
+  S.mode = c->moded.p + (size_t)p * c->S_alloc;
+  return S;
+}
+
 bool ngram_on(const nc_ctx* c) {
   return (c->cfg.features & (NC_F_NGRAM | NC_F_ENSEMBLE)) != 0;
 }
@@ -766,7 +783,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
     while (cap < 2 * (Ta + 1)) cap <<= 1;
     const int maxctx = std::min(Ta, c->cfg.ngram_max_contexts);
     c->b.alloc((size_t)Sa * V);
-    c->png.alloc((size_t)Sa * V);
+    c->png.alloc((size_t)2 * Sa * V);  // two parities (pipelined encode), parity 0 otherwise
     if (c->cfg.features & NC_F_ENSEMBLE) c->pk.alloc((size_t)Sa * K * V);
     c->lw.alloc((size_t)Sa * kMaxExperts);
     c->Hd.alloc(Sa);
@@ -777,7 +794,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
     c->nseen.alloc(Sa);
     c->hist.alloc((size_t)Sa * Ta);
     c->ncommit.alloc(Sa);
-    c->moded.alloc(Sa);
+    c->moded.alloc((size_t)2 * Sa);
     c->next_ctx.alloc((size_t)Sa * kMaxOrder);
     c->nctx.alloc((size_t)Sa * K);
     if (ngram_on(c)) {
@@ -834,6 +851,8 @@ StepArgs step_args(nc_ctx* c, int B, bool decode) {
   A.ng_parts = c->ngp.p;
   A.out = c->outc.p;
   A.step_out = c->sout.p;
+  A.pos = -1;
+  A.upd = kUpdCounts | kUpdMixer;
   return A;
 }
 
@@ -850,6 +869,35 @@ void vocab_commit_step(nc_ctx* c, const StepArgs& A) {
                          A.out, c->st);
     prof_end(c, NC_K_NGRAM, A.B * V * 4.0 * 2, A.B * V * 8.0);
   }
+}
+
+// One position of the batched encode, every row at position pos, in two streams:
+//   st:  the distribution of pos (n-gram parity pos % 2), its interval and bias step, and the
+//        mixer update, which needs the step's outcome;
+//   st2: the count updates with the known token t_pos, then the n-gram prediction of pos + 1
+//        into the other parity, which the distribution of pos - 1 was the last to read.
+// st waits for the prediction of pos (ev_pred); st2 waits for the distribution of pos - 1
+// (ev_dist of its parity; at pos 0 for everything st has queued).  Every kernel computes what the
+// sequential step computes, so the coded bytes are the same.
+void encode_step_pipelined(nc_ctx* c, StepArgs A, int pos) {
+  const double V = c->V;
+  const int par = pos & 1;
+  const StreamState Sp = state_par(c, par), Sn = state_par(c, par ^ 1);
+  A.pos = pos;
+  if (pos > 0) NC_HIP(hipStreamWaitEvent(c->st, c->ev_pred, 0));
+  prof_begin(c, NC_K_VOCAB);
+  launch_vocab_dist(c->vp, Sp, A, c->st);
+  A.upd = kUpdMixer;
+  launch_ngram_update(c->vp, Sp, A, c->st);
+  prof_end(c, NC_K_VOCAB, A.B * V * 4.0 * (2 + 2 + 2 + 2 + 1), A.B * V * 12.0);
+  NC_HIP(hipEventRecord(c->ev_dist[par], c->st));
+  NC_HIP(hipStreamWaitEvent(c->st2, c->ev_dist[pos > 0 ? par ^ 1 : par], 0));
+  A.upd = kUpdCounts;
+  launch_ngram_update(c->vp, Sn, A, c->st2);
+  prof_begin(c, NC_K_NGRAM, c->st2);
+  launch_ngram_predict(c->vp, Sn, A.rows, A.B, c->ngp.p, nullptr, nullptr, c->st2, pos + 1);
+  prof_end(c, NC_K_NGRAM, A.B * V * 4.0 * 2, A.B * V * 8.0, c->st2);
+  NC_HIP(hipEventRecord(c->ev_pred, c->st2));
 }
 
 void check_config(const nc_config* cfg) {
@@ -898,6 +946,9 @@ nc_status nc_create(const nc_config* cfg, const float* w, nc_ctx** out) {
     c->cfg = *cfg;
     NC_HIP(hipGetDevice(&c->dev));
     NC_HIP(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
+    NC_HIP(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&c->ev_dist[0], &c->ev_dist[1], &c->ev_pred})
+      NC_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     c->prec = cfg->precision == NC_FP32 ? P_F32 : cfg->precision == NC_BF16 ? P_BF16 : P_FP8;
     c->att = c->prec == P_F32 ? P_F32 : P_BF16;
     c->d = cfg->d_model;
@@ -1183,6 +1234,9 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
     if (ngram_on(c))
       launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
     const int C = c->cfg.slide;
+    // the n-gram chain of position i + 1 can run beside the distribution of position i when no
+    // ensemble experts (P_1..P_K, single-buffered) are involved
+    const bool pipe = ngram_on(c) && !(c->cfg.features & NC_F_ENSEMBLE);
     for (size_t a = 0; a < maxn; a += C) {
       // prefill: x positions [a, a + C) of every stream still active (teacher forcing)
       std::vector<RowMeta> rows;
@@ -1224,10 +1278,14 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
           A.step_out = nullptr;
           A.iv = c->iv.p;
           A.ptok = c->ptok.p;
-          vocab_commit_step(c, A);
+          if (pipe)
+            encode_step_pipelined(c, A, int(a + i));
+          else
+            vocab_commit_step(c, A);
         }
       }
     }
+    if (pipe) NC_HIP(hipStreamWaitEvent(c->st, c->ev_pred, 0));
     sync(c);
     // host coder, one thread per stream
     std::vector<std::vector<uint32_t>> ivs(n);

@@ -97,15 +97,31 @@ struct StepArgs {
   float* dbg_p;
   float* dbg_pt;
   uint32_t* dbg_cdf;
+  // Batched encode: every row is at position pos (>= 0), known to the host, and the update kernel
+  // takes the committed token from hist; -1: the position is S.ncommit[stream].
+  int pos;
+  // Updates run by the n-gram update kernel: kUpdCounts (token history, unigram and n-gram
+  // counts, next contexts, ncommit) and / or kUpdMixer (mixer weights or ensemble gate, which
+  // need the step's outcome).
+  int upd;
 };
+constexpr int kUpdCounts = 1, kUpdMixer = 2;
 
 // V1-V3, V4 for the ensemble and the V5 n-gram / mixer update (unless A.no_update)
 void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArgs& A,
                        hipStream_t s);
 // n-gram distribution, entropy and mode of the current position of each row's stream; with
 // step_out, also packs the step's outcome and the next mode for the host (decode).
+// pos: the rows' position (>= 0, batched encode) or -1 (S.ncommit).
 void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
-                          NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s);
+                          NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s,
+                          int pos = -1);
+// Only the step's distribution, interval and bias step (V1-V3, V4 for the ensemble), and only
+// the n-gram update kernel with the updates in A.upd.
+void launch_vocab_dist(const VocabParams& P, const StreamState& S, const StepArgs& A,
+                       hipStream_t s);
+void launch_ngram_update(const VocabParams& P, const StreamState& S, const StepArgs& A,
+                         hipStream_t s);
 void launch_state_reset(const VocabParams& P, const StreamState& S, int n_streams, float w_llm,
                         hipStream_t s);
 // Standalone ensemble head (C ABI): forward and backward over `rows` rows sharing b and theta.
