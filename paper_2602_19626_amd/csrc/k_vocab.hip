@@ -960,7 +960,7 @@ void launch_vocab_dist(const VocabParams& P, const StreamState& S, const StepArg
   if (A.B <= 0) return;
   const int nseg = int(ceil_div(P.V, kSeg));
   const dim3 grid(nseg, A.B);
-  hipLaunchKernelGGL(vocab_lse_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
+  if (A.lse) hipLaunchKernelGGL(vocab_lse_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
   hipLaunchKernelGGL(vocab_count_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
   hipLaunchKernelGGL(vocab_scan_kernel, grid, dim3(kSegThreads), 0, s, P, S, A);
   if (!A.no_update && P.ensemble)

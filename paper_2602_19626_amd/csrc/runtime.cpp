@@ -853,6 +853,7 @@ StepArgs step_args(nc_ctx* c, int B, bool decode) {
   A.step_out = c->sout.p;
   A.pos = -1;
   A.upd = kUpdCounts | kUpdMixer;
+  A.lse = 1;
   return A;
 }
 
@@ -1388,6 +1389,7 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
       c->stats.skipped += B - llm.size();
       StepArgs A = step_args(c, B, true);
       A.targets = reinterpret_cast<const uint32_t*>(dst + off_tg);
+      A.lse = llm.empty() ? 0 : 1;  // every row skips the model: no logsumexp needed
       vocab_commit_step(c, A);
       if (!ngram_on(c)) {
         // no n-gram stage: pack the outcome here (mode stays LLM)

@@ -104,6 +104,9 @@ struct StepArgs {
   // counts, next contexts, ncommit) and / or kUpdMixer (mixer weights or ensemble gate, which
   // need the step's outcome).
   int upd;
+  // 0: no row of the step uses the model's logits (every mode is skip), so the logsumexp pass is
+  // not launched
+  int lse;
 };
 constexpr int kUpdCounts = 1, kUpdMixer = 2;
 
