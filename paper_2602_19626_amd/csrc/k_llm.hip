@@ -804,7 +804,12 @@ constexpr int SPLIT_WAVES = 16;
 constexpr int SPLIT_ROWS = 64;
 constexpr int kSsqPre = 4;    // staged block sums of squares held per thread during the parts
 constexpr int kSsqStage = 64;  // staged only for K <= 16 * kSsqStage
-constexpr int SKINNY_ROWS = 256;  // below this many rows the split kernel is used
+// Fixed rule (used without tuning): the split kernel below SKINNY_ROWS rows, the 64 x 64 tile
+// kernel below WIDE_ROWS, the 128 x 128 wide kernel (BF16 / FP8) above; at a few hundred rows the
+// wide kernel has too few tiles to fill the chip (the tuner measured the split kernel 3-6x faster
+// there).
+constexpr int SKINNY_ROWS = 512;
+constexpr int WIDE_ROWS = 4096;
 
 // inv[a_rows[m]] = the RMSNorm scale of row a_rows[m] (for the output layer)
 __global__ void row_rms_kernel(const GemmArgs a, float* __restrict__ inv) {
@@ -1537,7 +1542,7 @@ static GemmTile default_tile(int prec, int epi, const GemmArgs& a) {
   const int S = split_parts(a);
   const GemmTile sp{T_SPLIT, split_mb(a, epi), S < SPLIT_WAVES ? S : SPLIT_WAVES};
   if (a.M < SKINNY_ROWS && split_lds(a, epi, sp.mb) <= kSplitLdsMax) return sp;
-  if (a.M >= SKINNY_ROWS && wide_ok(prec, epi, a)) return GemmTile{T_WIDE, 0, 0};
+  if (a.M >= WIDE_ROWS && wide_ok(prec, epi, a)) return GemmTile{T_WIDE, 0, 0};
   return GemmTile{a.M <= 64 ? T_TILE_S : T_TILE_M, 0, 0};
 }
 
