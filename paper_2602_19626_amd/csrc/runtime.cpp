@@ -125,6 +125,10 @@ struct nc_ctx {
   DevBuf<NgPart> ngp;
   DevBuf<Outcome> outc;
   DevBuf<StepOut> sout;
+  // decode: step outputs written by the device straight into mapped pinned host memory
+  StepOut* sout_h = nullptr;   // host view
+  StepOut* sout_hd = nullptr;  // device view of the same memory
+  int sout_h_n = 0;
   DevBuf<float> dbgp, dbgpt;
   DevBuf<uint32_t> dbgcdf;
   // pinned host staging
@@ -177,6 +181,7 @@ nc_ctx::~nc_ctx() {
   sout.release();
   if (pin) (void)hipHostFree(pin);
   if (spin) (void)hipHostFree(spin);
+  if (sout_h) (void)hipHostFree(sout_h);
   dstage.release();
   for (auto e : ev_free) (void)hipEventDestroy(e);
   for (auto& pr : ev_busy) {
@@ -371,6 +376,15 @@ void ensure_step(nc_ctx* c, int B) {
   c->ngp.alloc((size_t)B * nseg);
   c->outc.alloc(B);
   c->sout.alloc(B);
+  if (B > c->sout_h_n) {
+    if (c->sout_h) NC_HIP(hipHostFree(c->sout_h));
+    c->sout_h = nullptr;
+    c->sout_h_n = 0;
+    NC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->sout_h), size_t(B) * sizeof(StepOut),
+                         hipHostMallocMapped | hipHostMallocCoherent));
+    NC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->sout_hd), c->sout_h, 0));
+    c->sout_h_n = B;
+  }
 }
 
 // ---- one transformer pass over a batch of rows --------------------------------------------
@@ -1390,6 +1404,7 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
       StepArgs A = step_args(c, B, true);
       A.targets = reinterpret_cast<const uint32_t*>(dst + off_tg);
       A.lse = llm.empty() ? 0 : 1;  // every row skips the model: no logsumexp needed
+      A.step_out = c->sout_hd;      // the outcome goes straight to host memory
       vocab_commit_step(c, A);
       if (!ngram_on(c)) {
         // no n-gram stage: pack the outcome here (mode stays LLM)
@@ -1397,7 +1412,8 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
         d2h(c, oc.data(), c->outc.p, B);
         for (int k = 0; k < B; ++k) so[k] = StepOut{oc[k].sym, oc[k].cl, oc[k].ch, M_LLM, oc[k].p};
       } else {
-        d2h(c, so.data(), c->sout.p, B);
+        sync(c);
+        std::memcpy(so.data(), c->sout_h, size_t(B) * sizeof(StepOut));
       }
       for (int k = 0; k < B; ++k) {
         const int s = order[k];
