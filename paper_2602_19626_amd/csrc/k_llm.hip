@@ -790,14 +790,14 @@ static void gemm_wide(const GemmArgs& a, hipStream_t s) {
                      tn);
 }
 
-// ---- split kernel (fewer than 256 rows): one workgroup per (epilogue group, 64-row chunk) ----
+// ---- split kernel (few rows): one workgroup per (epilogue group, chunk of mb 16-row blocks) ----
 //
 // A group is the set of 16-column blocks one epilogue needs together: a RoPE pair of blocks
 // {b, b + hd/32} for QKV (a single block when hd = 16), a gate/up block pair for the SiLU-gated
-// MLP, two adjacent blocks for plain stores, one block for residual adds.  Wave w takes K parts
-// w, w + nw, ...: for a part it issues the loads of the chunk's A fragments and the group's W
-// fragments together, runs every (row block, column block) MFMA chain from zero and leaves the
-// partial in LDS.  After one barrier the workgroup adds each output's partials in part order and
+// MLP, two adjacent blocks for plain stores, one block for residual adds.  A chunk holds mb
+// (1-4) blocks of 16 rows.  Wave w of nw takes K parts w, w + nw, ...: for a part it issues the
+// loads of the chunk's A fragments and the group's W fragments together, runs every (row block,
+// column block) MFMA chain from zero and leaves the partial in LDS.  After one barrier the workgroup adds each output's partials in part order and
 // applies the epilogue.  No cross-workgroup communication is needed.
 
 constexpr int SPLIT_WAVES = 16;

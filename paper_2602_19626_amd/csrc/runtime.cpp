@@ -1459,7 +1459,6 @@ nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out,
     sync(c);
     if (c->S_alloc < 1) reset_streams(c, 1, 1);
     const int Mmax = int(max_rows);
-    // output-layer GEMMs only ever see one row per stream
     // output-layer GEMMs see one row per stream (decode) or an encode chunk of positions
     const int Mlm = std::min(Mmax, std::max(c->cfg.max_streams, kEncodeHeadRows));
     ensure_rows(c, Mmax);
