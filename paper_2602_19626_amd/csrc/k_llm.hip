@@ -303,6 +303,17 @@ struct Frag<P_F32> {
       for (int e = 0; e < 4; ++e) f[4 * q + e] = v[e];
     }
   }
+  // as load_raw, but the load itself is unconditional (its offset clamped into the row), so that
+  // no branch separates it from the loads issued around it
+  __device__ static void load_clamped(T& f, const uint8_t* row, int k0, int K, int g) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 16 * g + 4 * q;
+      const v4f v = *reinterpret_cast<const v4f*>(row + (long long)min(k, K - 4) * 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f[4 * q + e] = k < K ? v[e] : 0.f;
+    }
+  }
   __device__ static void mma(v4f& acc, const T& a, const T& b) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[t], acc, 0, 0, 0);
@@ -321,6 +332,14 @@ struct Frag<P_BF16> {
     for (int t = 0; t < 2; ++t) {
       const int k = k0 + 32 * t + 8 * g;
       f[t] = k < K ? *reinterpret_cast<const v4i*>(row + (long long)k * 2) : v4i{0, 0, 0, 0};
+    }
+  }
+  __device__ static void load_clamped(T& f, const uint8_t* row, int k0, int K, int g) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = k0 + 32 * t + 8 * g;
+      const v4i v = *reinterpret_cast<const v4i*>(row + (long long)min(k, K - 8) * 2);
+      f[t] = k < K ? v : v4i{0, 0, 0, 0};
     }
   }
   __device__ static void mma(v4f& acc, const T& a, const T& b) {
@@ -343,6 +362,14 @@ struct Frag<P_FP8> {
     for (int t = 0; t < 2; ++t) {
       const int k = k0 + 32 * t + 8 * g;
       f[t] = k < K ? *reinterpret_cast<const long*>(row + k) : 0;
+    }
+  }
+  __device__ static void load_clamped(T& f, const uint8_t* row, int k0, int K, int g) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = k0 + 32 * t + 8 * g;
+      const long v = *reinterpret_cast<const long*>(row + min(k, K - 8));
+      f[t] = k < K ? v : 0;
     }
   }
   __device__ static void mma(v4f& acc, const T& a, const T& b) {
@@ -852,9 +879,62 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   float* s_ssq = s_inv + SPLIT_ROWS;  // [row][K / 16] when staged
   const uint8_t* A8 = static_cast<const uint8_t*>(a.A);
   const uint8_t* W8 = static_cast<const uint8_t*>(a.W);
+  // only the output layer gathers its A rows (launch_gemm checks this); elsewhere the row of
+  // output m is r0 + m and the prologue has no gather loads
+  const int32_t* const a_rows = EPI == E_STORE ? a.a_rows : nullptr;
+  // Every load of the prologue and of the parts is issued unconditionally (indices clamped into
+  // range; values past the end are masked afterwards or never stored).  A load skipped by a
+  // branch would make the count of loads in flight path-dependent, and the wait for an earlier
+  // load would then have to drain every later one: the operands' loads would wait for the weight
+  // loads issued before them, one memory round trip after the other.  For the same reason a wave
+  // without parts still issues the first part's loads, of a few bytes at the start of the
+  // operands.
+  constexpr int NBUF = EPI == E_RESID ? 2 : 1;
+  typename Frag<P>::T bf[NBUF][2], af[NBUF][MB];
+  const bool real = wave < S;  // wave-uniform
+  // columns past N repeat column N - 1 (never stored); K entries past K are zero in both operands
+  auto load_w = [&](int s, int q, bool use) {
+    const int k0 = use ? s * KP : 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      // both blocks are loaded whenever the group size is not known at compile time (QKV with
+      // hd = 16 uses one), so that the count of loads does not depend on it
+      if (EPI == E_RESID && j >= 1) break;
+      const int n = use ? min(group_block(EPI, a.hd, gi, j) * 16 + fr, N - 1) : 0;
+      Frag<P>::load_clamped(bf[q][j], W8 + (long long)n * K * ES, k0, K, fg);
+    }
+  };
+  // This lane's A row of each row block (rows past M repeat row M - 1; their outputs are never
+  // stored), resolved once for every part.
+  int arow[MB];
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb) arow[rb] = r0 + min(rb * 16 + fr, M - 1);
+  // (a wave without parts reads the start of its first A row: with gathered rows, output row
+  // indices are not A row indices, and the output layer may have more output rows than A rows)
+  auto load_a = [&](int s, int q, bool use) {
+    const int k0 = use ? s * KP : 0;
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+      Frag<P>::load_clamped(af[q][rb], A8 + (long long)(use ? arow[rb] : arow[0]) * K * ES, k0, K,
+                            fg);
+  };
+  // Issue order of the first part: the output layer's weights go out ahead of its gathered rows
+  // (the first wait for those also covers the weights, issued just before); elsewhere the row
+  // statistics go first, so that the row scales can be prepared while the weights and operand
+  // rows are still in flight.
+  if constexpr (EPI == E_STORE) load_w(real ? wave : 0, 0, real);
+  if (a_rows) {
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb) arow[rb] = a_rows[arow[rb]];
+  }
+  // A row of output row r0 + t for the given row scales, t = threadIdx.x < M (all in wave 0):
+  // lane t holds it as arow[t / 16], with no load of its own
+  int ar_t = arow[0];
+#pragma unroll
+  for (int rb = 1; rb < MB; ++rb) ar_t = (lane >> 4) == rb ? arow[rb] : ar_t;
   // Row scales of a normed GEMM: their inputs (the block sums of squares, or the given scales)
-  // are loaded before the parts' operands, so that their latency overlaps the parts' loads
-  // instead of following the last MFMA.
+  // are loaded before the parts' operands are consumed, so that their latency overlaps the
+  // parts' loads instead of following the last MFMA.
   const int nb16 = K / 16;
   const int nss = (AM == A_NORM && !a.inv) ? M * nb16 : 0;
   const bool staged = nss > 0 && nb16 <= kSsqStage && nss <= kSsqPre * int(blockDim.x);
@@ -863,16 +943,13 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   if (staged) {
 #pragma unroll
     for (int k = 0; k < kSsqPre; ++k) {
-      const int i = threadIdx.x + k * int(blockDim.x);
-      if (i < nss) {
-        const int m = i / nb16;
-        const int ar = a.a_rows ? a.a_rows[r0 + m] : r0 + m;
-        pre[k] = a.ssq[(long long)ar * nb16 + (i - m * nb16)];
-      }
+      const int i = min(int(threadIdx.x) + k * int(blockDim.x), nss - 1);
+      const int m = i / nb16;
+      const int ar = a_rows ? a_rows[r0 + m] : r0 + m;
+      pre[k] = a.ssq[(long long)ar * nb16 + (i - m * nb16)];
     }
-  } else if (AM == A_NORM && a.inv && int(threadIdx.x) < M) {
-    pre_inv = a.inv[a.a_rows ? a.a_rows[r0 + threadIdx.x] : r0 + threadIdx.x];
   }
+  if constexpr (EPI != E_STORE) load_w(real ? wave : 0, 0, real);
   // The inputs of this thread's first epilogue item are fetched now as well: the row metadata of
   // a q/k/v output (its RoPE entry follows once the metadata is in), or the residual value and
   // gain of a residual output.
@@ -880,38 +957,26 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   float2 pre_cs{1.f, 0.f};
   float pre_x = 0.f, pre_g = 0.f;
   if constexpr (EPI == E_QKV) {
-    if (int(threadIdx.x) < M * gs * 16) pre_rm = a.rows[r0 + threadIdx.x / (gs * 16)];
+    pre_rm = a.rows[r0 + min(int(threadIdx.x) / (gs * 16), M - 1)];
   } else if constexpr (EPI == E_RESID) {
-    const int t = threadIdx.x, n = gi * 16 + (t & 15);
-    if (t < M * 16 && n < N) {
-      pre_x = a.out_f32[(long long)(r0 + (t >> 4)) * a.ldo + n];
-      if (a.y_out) pre_g = a.y_gain[n];
-    }
+    const int t = threadIdx.x;
+    const int m = min(t >> 4, M - 1), n = min(gi * 16 + (t & 15), N - 1);
+    const float* xp = a.out_f32 + (long long)(r0 + m) * a.ldo + n;
+    pre_x = *xp;
+    pre_g = *(a.y_out ? a.y_gain + n : xp);  // (unused without y_out)
   }
-  // residual GEMMs include the long-K down projection, whose waves own two parts: there the
-  // second part's loads go out with the first's (a second register buffer)
-  constexpr int NBUF = EPI == E_RESID ? 2 : 1;
-  typename Frag<P>::T bf[NBUF][2], af[NBUF][MB];
+  load_a(real ? wave : 0, 0, real);
+  if constexpr (AM == A_NORM) {
+    // only wave 0 uses it (and only with given scales); the other waves read the start of a
+    // weight row they load anyway rather than all hitting one line
+    const float* ip = a.inv ? a.inv + ar_t : a.ssq;
+    if (wave != 0) ip = reinterpret_cast<const float*>(W8 + (long long)min(gi * 16, N - 1) * K * ES);
+    pre_inv = *ip;
+  }
+  // a later part: weights and operand rows together
   auto load_part = [&](int s, int q) {
-    const int k0 = s * KP;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = group_block(EPI, a.hd, gi, j) * 16 + fr;
-      if (j < gs && n < N)
-        Frag<P>::load_raw(bf[q][j], W8 + (long long)n * K * ES, k0, K, fg);
-      else
-        Frag<P>::zero(bf[q][j]);
-    }
-#pragma unroll
-    for (int rb = 0; rb < MB; ++rb) {
-      const int m = rb * 16 + fr;
-      if (m < M) {
-        const int ar = a.a_rows ? a.a_rows[r0 + m] : r0 + m;
-        Frag<P>::load_raw(af[q][rb], A8 + (long long)ar * K * ES, k0, K, fg);
-      } else {
-        Frag<P>::zero(af[q][rb]);
-      }
-    }
+    load_w(s, q, true);
+    load_a(s, q, true);
   };
   auto compute_part = [&](int s, int q) {
 #pragma unroll
@@ -927,41 +992,54 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       }
     }
   };
+  // the RoPE entry of this thread's first q/k output (its metadata was requested first); every
+  // thread loads one (a valid table entry for any column), the epilogue uses those of q/k outputs
+  auto qkv_cs = [&]() {
+    if constexpr (EPI == E_QKV) {
+      const int t = threadIdx.x;
+      const int n = group_block(EPI, a.hd, gi, (t >> 4) % gs) * 16 + (t & 15);
+      pre_cs = rope_cs(a, pre_rm.pos, n);
+    }
+  };
+  // the chunk's row scales into s_inv (read after the barrier that follows the parts)
+  auto row_scales = [&]() {
+    if (staged) {
+#pragma unroll
+      for (int k = 0; k < kSsqPre; ++k) {
+        const int i = threadIdx.x + k * int(blockDim.x);
+        if (i < nss) s_ssq[i] = pre[k];
+      }
+      __syncthreads();
+      for (int m = threadIdx.x; m < M; m += blockDim.x)
+        s_inv[m] = inv_from_ssq(s_ssq + m * nb16, K, a.eps);
+    } else if (AM == A_NORM && a.inv) {
+      if (int(threadIdx.x) < M) s_inv[threadIdx.x] = pre_inv;
+      for (int m = threadIdx.x + blockDim.x; m < M; m += blockDim.x)
+        s_inv[m] = a.inv[a_rows ? a_rows[r0 + m] : r0 + m];
+    } else {
+      for (int m = threadIdx.x; m < M; m += blockDim.x)
+        s_inv[m] = AM == A_NORM ? a_row_inv(a, a_rows ? a_rows[r0 + m] : r0 + m) : 1.f;
+    }
+  };
   // parts wave, wave + nw, ...
   if constexpr (NBUF == 2) {
     for (int s = wave; s < S; s += 2 * nw) {
-      load_part(s, 0);
+      if (s != wave) load_part(s, 0);
       if (s + nw < S) load_part(s + nw, NBUF - 1);
       compute_part(s, 0);
       if (s + nw < S) compute_part(s + nw, NBUF - 1);
     }
+    qkv_cs();
+    row_scales();
   } else {
+    // The first part's operands are in flight (issued above) while the row scales and the RoPE
+    // entries are prepared.  Every wave reaches the scales' barrier.
+    row_scales();
+    qkv_cs();
     for (int s = wave; s < S; s += nw) {
-      load_part(s, 0);
+      if (s != wave) load_part(s, 0);
       compute_part(s, 0);
     }
-  }
-  if constexpr (EPI == E_QKV) {
-    const int t = threadIdx.x;
-    const int n = group_block(EPI, a.hd, gi, (t >> 4) % gs) * 16 + (t & 15);
-    if (t < M * gs * 16 && n < (a.Hq + a.Hk) * a.hd) pre_cs = rope_cs(a, pre_rm.pos, n);
-  }
-  if (staged) {
-#pragma unroll
-    for (int k = 0; k < kSsqPre; ++k) {
-      const int i = threadIdx.x + k * int(blockDim.x);
-      if (i < nss) s_ssq[i] = pre[k];
-    }
-    __syncthreads();
-    for (int m = threadIdx.x; m < M; m += blockDim.x)
-      s_inv[m] = inv_from_ssq(s_ssq + m * nb16, K, a.eps);
-  } else if (AM == A_NORM && a.inv) {
-    if (int(threadIdx.x) < M) s_inv[threadIdx.x] = pre_inv;
-    for (int m = threadIdx.x + blockDim.x; m < M; m += blockDim.x)
-      s_inv[m] = a.inv[a.a_rows ? a.a_rows[r0 + m] : r0 + m];
-  } else {
-    for (int m = threadIdx.x; m < M; m += blockDim.x)
-      s_inv[m] = AM == A_NORM ? a_row_inv(a, a.a_rows ? a.a_rows[r0 + m] : r0 + m) : 1.f;
   }
   __syncthreads();
   const float deq = (P == P_FP8) ? a.a_scale * a.w_scale : 1.0f;
@@ -1613,6 +1691,7 @@ void launch_gemm(int prec, int amode, int epi, const GemmArgs& a, hipStream_t s,
   if (epi == E_QKV) NC_CHECK(64 % a.hd == 0, NC_E_INVALID, "head_dim must divide 64");
   if (epi == E_GLU) NC_CHECK(a.N % 32 == 0, NC_E_INVALID, "d_ffn must be a multiple of 16");
   if (amode == A_NORM) NC_CHECK(a.ssq || a.inv, NC_E_INVALID, "normed GEMM needs row statistics");
+  NC_CHECK(!a.a_rows || epi == E_STORE, NC_E_INVALID, "only the output layer gathers A rows");
   if (epi == E_RESID)
     NC_CHECK(a.N % 16 == 0 && (!a.y_out || a.y_gain), NC_E_INVALID, "bad residual epilogue");
   NC_CHECK(tile_valid(prec, epi, a, t), NC_E_INVALID, "GEMM launch shape does not fit this GEMM");

@@ -65,19 +65,29 @@ __device__ __forceinline__ float row_prob_v(const RowIn& R, int t, float z, floa
   if (R.mode == M_SKIP) return g;
   if (R.mode == M_MIX) return R.w[0] * q + R.w[1] * g;
   float p = R.w[0] * q;
-  for (int j = 1; j <= R.K; ++j) p = p + R.w[j] * R.pk[(size_t)(j - 1) * R.V + t];
+  // orders unrolled to the compile-time bound so that w stays in registers
+#pragma unroll
+  for (int j = 1; j <= kMaxOrder; ++j)
+    if (j <= R.K) p = p + R.w[j] * R.pk[(size_t)(j - 1) * R.V + t];
   return p;
 }
 
 // Mixture / gate weights of a stream: mixer w = exp(log w); ensemble w = softmax(theta).
 __device__ __forceinline__ void row_weights(const VocabParams& P, const float* lw, float* w) {
   if (P.ensemble) {
+    // loops unrolled to the compile-time bound (n <= kMaxOrder + 1) so that w stays in registers
     const int n = P.K + 1;
     float mx = lw[0];
-    for (int j = 1; j < n; ++j) mx = fmaxf(mx, lw[j]);
+#pragma unroll
+    for (int j = 1; j <= kMaxOrder; ++j)
+      if (j < n) mx = fmaxf(mx, lw[j]);
     float s = 0.f;
-    for (int j = 0; j < n; ++j) s += expf(lw[j] - mx);
-    for (int j = 0; j < n; ++j) w[j] = expf(lw[j] - mx) / s;
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j)
+      if (j < n) s += expf(lw[j] - mx);
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j)
+      if (j < n) w[j] = expf(lw[j] - mx) / s;
   } else {
     w[0] = expf(lw[0]);
     w[1] = expf(lw[1]);
@@ -246,7 +256,9 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
   // fetched with the row, not after the scan
   const int i_pos = !active ? 0 : (A.pos >= 0 ? A.pos : S.ncommit[s]);
   const uint32_t key =
-      !active ? 0u : (A.decode ? A.targets[r] : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
+      !active ? 0u
+              : (A.decode ? (A.targets ? A.targets[r] : A.targets_in[r])
+                          : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
   RowIn R;
   RowVec v;
   float p[4][4], pt[4][4];
@@ -267,7 +279,7 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
   seg_scan(p, seg, V, q, base, L, tid);
   int found = -1;
   uint32_t fcl = 0, fch = 0;
-  float fp = 0.f, fpt = 0.f;
+  float fp = 0.f, fpt = 0.f, fpng = 0.f;
   if (active) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -284,6 +296,7 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
             fch = run + c;
             fp = p[j][i];
             fpt = pt[j][i];
+            fpng = v.g[j][i];  // the row's p_ng at t, fetched with the row
           }
           if (A.dbg_cdf) A.dbg_cdf[(size_t)r * (V + 1) + t + 1] = run + c;
           if (A.dbg_p) A.dbg_p[(size_t)r * V + t] = p[j][i];
@@ -302,14 +315,16 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
       o.mode = R.mode;
       o.p = fp;
       o.pt = fpt;
-      o.png = R.png[found];
+      o.png = fpng;
       o.lse = R.lse;
       for (int k = 0; k < kMaxOrder; ++k)
         o.pk[k] = (R.pk && k < P.K) ? R.pk[(size_t)k * V + found] : 0.f;
       for (int k = 0; k < kMaxExperts; ++k) o.r[k] = 0.f;
       if (R.mode == M_ENS) {
         o.r[0] = R.w[0] * fpt / fp;
-        for (int k = 1; k <= P.K; ++k) o.r[k] = R.w[k] * o.pk[k - 1] / fp;
+#pragma unroll
+        for (int k = 1; k <= kMaxOrder; ++k)
+          if (k <= P.K) o.r[k] = R.w[k] * o.pk[k - 1] / fp;
       }
       A.out[r] = o;
       if (A.iv) {
@@ -441,7 +456,9 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
     } else if (o.mode == M_ENS) {
       float w[kMaxExperts];
       row_weights(P, lw, w);
-      for (int j = 0; j <= P.K; ++j) lw[j] = lw[j] - P.head_lr * (w[j] - o.r[j]);
+#pragma unroll
+      for (int j = 0; j <= kMaxOrder; ++j)
+        if (j <= P.K) lw[j] = lw[j] - P.head_lr * (w[j] - o.r[j]);
     }
   }
   if (on && counts && (P.use_ngram || P.ensemble) && k >= 1 && k <= P.K) {
@@ -536,7 +553,7 @@ __device__ __forceinline__ float ng_base(const StreamState& S, const NgRow& g, i
 }
 
 __device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& S,
-                                       const int32_t* rows, NgPart* parts, int seg, int r,
+                                       const RowList& rows, NgPart* parts, int seg, int r,
                                        int nseg, int tid, bool active, NgPart* wl) {
   const int lane = tid & 63, w = tid >> 6;
   const int V = P.V;
@@ -597,30 +614,54 @@ struct FixLds {
 
 // 256 threads (tid) of one row; active == false only passes the barriers
 __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& S,
-                                       const int32_t* rows, const NgPart* parts, int nseg,
+                                       const RowList& rows, const NgPart* parts, int nseg,
                                        StepOut* step_out, const Outcome* out, int r, int tid,
                                        bool active, FixLds& F, int pos_given) {
   const int nt = kSegThreads;
   const int V = P.V;
   const int s = rows[r];
+  // inputs of the final reduction and of the packed outcome, fetched now so that their latency
+  // overlaps the n-gram chain below
+  NgPart pre_part{0.f, 0.f};
+  if (active && tid < nseg) pre_part = parts[(size_t)r * nseg + tid];
+  int pre_pos = 0, pre_sym = 0;
+  uint32_t pre_cl = 0, pre_ch = 0;
+  float pre_p = 0.f;
+  if (active && tid == 0) {
+    pre_pos = pos_given >= 0 ? pos_given : S.ncommit[s];
+    if (step_out) {
+      pre_sym = out[r].sym;
+      pre_cl = out[r].cl;
+      pre_ch = out[r].ch;
+      pre_p = out[r].p;
+    }
+  }
   NgRow g{};
   if (active) g = ng_row(P, S, s);
   if (active && tid < kMaxOrder) F.ln[tid] = 0;
   __syncthreads();
-  if (active)
-    for (int e = tid; e < P.K * kSlots; e += nt) {
-      const int k = e / kSlots + 1, j = e % kSlots;
-      if (!g.present[k - 1]) continue;
-      const int id = g.id[k - 1];
-      const size_t t = (size_t)s * P.K + (k - 1);
-      // the slot is read whether or not it is in use (readers stop at ln), so the slot and the
-      // slot count load together
-      const int2 tc = *reinterpret_cast<const int2*>(S.pool + ((t * S.maxctx + id) * kSlots + j) * 2);
-      const int n = S.pool_n[t * S.maxctx + id];
-      if (j == 0) F.ln[k - 1] = n;
-      F.lt[k - 1][j] = tc.x;
-      F.lc[k - 1][j] = tc.y;
+  // wave w reads the kSlots slots of order w + 1 (one slot per lane), so the order is
+  // wave-uniform and the row's per-order values are picked without indexing
+  static_assert(kSlots == 64 && kMaxOrder * kSlots <= kSegThreads, "one wave per order");
+  const int kw = __builtin_amdgcn_readfirstlane(tid >> 6);  // order - 1 of this wave
+  int w_present = 0, w_id = -1;
+#pragma unroll
+  for (int q = 0; q < kMaxOrder; ++q)
+    if (kw == q) {
+      w_present = g.present[q];
+      w_id = g.id[q];
     }
+  if (active && kw < P.K && w_present) {
+    const int k = kw + 1, j = tid & 63, id = w_id;
+    const size_t t = (size_t)s * P.K + (k - 1);
+    // the slot is read whether or not it is in use (readers stop at ln), so the slot and the
+    // slot count load together
+    const int2 tc = *reinterpret_cast<const int2*>(S.pool + ((t * S.maxctx + id) * kSlots + j) * 2);
+    const int n = S.pool_n[t * S.maxctx + id];
+    if (j == 0) F.ln[k - 1] = n;
+    F.lt[k - 1][j] = tc.x;
+    F.lc[k - 1][j] = tc.y;
+  }
   __syncthreads();
   float dh = 0.f, dmx = 0.f;
   if (active)
@@ -638,7 +679,9 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
       if (!owner) continue;
       // P_k(tok) = lambda_k Phat_k(tok) + (1 - lambda_k) P_{k-1}(tok), k = 1..K (section 3.5)
       float pv = ng_base(S, g, s, V, tok);
-      for (int k2 = 1; k2 <= P.K; ++k2) {
+#pragma unroll
+      for (int k2 = 1; k2 <= kMaxOrder; ++k2) {
+        if (k2 > P.K) break;
         if (g.present[k2 - 1]) {
           int cnt = 0;
           for (int j2 = 0; j2 < F.ln[k2 - 1]; ++j2)
@@ -662,9 +705,8 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
     F.smx[tid >> 6] = dmx;
   }
   if (active && tid < nseg) {
-    const NgPart q = parts[(size_t)r * nseg + tid];
-    F.sh[kSegWaves + tid] = q.h;
-    F.smx[kSegWaves + tid] = q.mx;
+    F.sh[kSegWaves + tid] = pre_part.h;
+    F.smx[kSegWaves + tid] = pre_part.mx;
   }
   __syncthreads();
   if (active && tid == 0) {
@@ -682,7 +724,7 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
     mx = fmaxf(mx, smx);
     S.H[s] = H;
     S.pmax[s] = mx;
-    const int pos = pos_given >= 0 ? pos_given : S.ncommit[s];
+    const int pos = pre_pos;
     int mode;
     if (P.ensemble) {
       mode = M_ENS;
@@ -697,13 +739,12 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
     }
     S.mode[s] = mode;
     if (step_out) {
-      const Outcome o = out[r];
       StepOut so{};
-      so.sym = o.sym;
-      so.cl = o.cl;
-      so.ch = o.ch;
+      so.sym = pre_sym;
+      so.cl = pre_cl;
+      so.ch = pre_ch;
       so.next_mode = mode;
-      so.p = o.p;
+      so.p = pre_p;
       step_out[r] = so;
     }
   }
@@ -741,14 +782,14 @@ __global__ __launch_bounds__(64) void ngram_update_kernel(VocabParams P, StreamS
 }
 
 __global__ __launch_bounds__(kSegThreads) void ngram_dense_kernel(VocabParams P, StreamState S,
-                                                                  const int32_t* rows,
+                                                                  const RowList rows,
                                                                   NgPart* parts) {
   __shared__ NgPart wl[kSegWaves];
   v6_seg(P, S, rows, parts, blockIdx.x, blockIdx.y, gridDim.x, threadIdx.x, true, wl);
 }
 
 __global__ __launch_bounds__(kSegThreads) void ngram_fix_kernel(VocabParams P, StreamState S,
-                                                                const int32_t* rows,
+                                                                const RowList rows,
                                                                 const NgPart* parts, int nseg,
                                                                 StepOut* step_out,
                                                                 const Outcome* out, int pos) {
@@ -981,7 +1022,7 @@ void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArg
   launch_ngram_update(P, S, A, s);
 }
 
-void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
+void launch_ngram_predict(const VocabParams& P, const StreamState& S, const RowList& rows, int B,
                           NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s,
                           int pos) {
   if (B <= 0) return;

@@ -119,6 +119,7 @@ struct nc_ctx {
   DevBuf<float> z;
   DevBuf<float> zseg;  // encode: logits of a chunk of positions [pos][stream slot][V]
   DevBuf<int32_t> steprows, arows;
+  std::vector<int32_t> hsteprows;  // host copy of steprows
   DevBuf<uint32_t> targets;
   DevBuf<LsePart> lsep;
   DevBuf<SegPartial> segp;
@@ -368,6 +369,7 @@ void ensure_rows(nc_ctx* c, int rows) {
 void ensure_step(nc_ctx* c, int B) {
   const int nseg = int(ceil_div(c->V, kSeg));
   c->z.alloc((size_t)B * c->V);
+  if (size_t(B) > c->steprows.n) c->hsteprows.clear();  // a new device list starts undefined
   c->steprows.alloc(B);
   c->arows.alloc(B);
   c->targets.alloc(B);
@@ -785,6 +787,23 @@ bool ngram_on(const nc_ctx* c) {
   return (c->cfg.features & (NC_F_NGRAM | NC_F_ENSEMBLE)) != 0;
 }
 
+// The stream of each step row (device list plus its host copy).
+void set_steprows(nc_ctx* c, const int32_t* rows, size_t n) {
+  h2d(c, c->steprows.p, rows, n);
+  c->hsteprows.assign(rows, rows + n);
+}
+
+// Row list of a step over steprows[0..B); small steps carry the rows by value as well.
+RowList row_list(nc_ctx* c, int B) {
+  RowList r{};
+  r.p = c->steprows.p;
+  if (B <= kRowsInline && B <= int(c->hsteprows.size())) {
+    r.n_in = B;
+    for (int i = 0; i < B; ++i) r.v[i] = c->hsteprows[i];
+  }
+  return r;
+}
+
 void reset_streams(nc_ctx* c, int n, int maxT) {
   NC_CHECK(n >= 1 && n <= c->cfg.max_streams, NC_E_INVALID, "n_streams must be in [1, %d]",
            c->cfg.max_streams);
@@ -845,8 +864,8 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
   if (ngram_on(c)) {
     std::vector<int32_t> ids(n);
     std::iota(ids.begin(), ids.end(), 0);
-    h2d(c, c->steprows.p, ids.data(), ids.size());
-    launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
+    set_steprows(c, ids.data(), ids.size());
+    launch_ngram_predict(c->vp, c->S, row_list(c, n), n, c->ngp.p, nullptr, nullptr, c->st);
   }
   sync(c);
   c->hhist.assign(n, {});
@@ -856,7 +875,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
 StepArgs step_args(nc_ctx* c, int B, bool decode) {
   StepArgs A{};
   A.B = B;
-  A.rows = c->steprows.p;
+  A.rows = row_list(c, B);
   A.z = c->z.p;
   A.decode = decode ? 1 : 0;
   A.targets = c->targets.p;
@@ -1137,7 +1156,7 @@ nc_status nc_probs_for_context(nc_ctx* c, uint32_t s, const int32_t* tokens, siz
       NC_CHECK(tokens[i] == h[i], NC_E_STATE, "history differs from the committed tokens at %zu",
                i);
     const int32_t sid = int32_t(s);
-    h2d(c, c->steprows.p, &sid, 1);
+    set_steprows(c, &sid, 1);
     // commit the new tokens one by one, exactly as the encoder does
     for (size_t j = h.size(); j < n; ++j) {
       NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc + j, tokens + j, 4,
@@ -1197,7 +1216,7 @@ nc_status nc_mix_update(nc_ctx* c, uint32_t s, int32_t token) {
     const size_t j = h.size();
     NC_CHECK(int(j) + 1 < c->maxT, NC_E_STATE, "stream is full (max_tokens reached)");
     const int32_t sid = int32_t(s);
-    h2d(c, c->steprows.p, &sid, 1);
+    set_steprows(c, &sid, 1);
     NC_HIP(hipMemcpyAsync(c->hist.p + (size_t)s * c->T_alloc + j, &token, 4,
                           hipMemcpyHostToDevice, c->st));
     catch_up_now(c, int(s), int(j));
@@ -1245,9 +1264,9 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
                             hipMemcpyHostToDevice, c->st));
     }
     sync(c);
-    h2d(c, c->steprows.p, order.data(), order.size());
+    set_steprows(c, order.data(), order.size());
     if (ngram_on(c))
-      launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
+      launch_ngram_predict(c->vp, c->S, row_list(c, n), n, c->ngp.p, nullptr, nullptr, c->st);
     const int C = c->cfg.slide;
     // the n-gram chain of position i + 1 can run beside the distribution of position i when no
     // ensemble experts (P_1..P_K, single-buffered) are involved
@@ -1371,7 +1390,7 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return n_tokens[a] > n_tokens[b]; });
-    h2d(c, c->steprows.p, order.data(), order.size());
+    set_steprows(c, order.data(), order.size());
     std::vector<ArithDecoder> dec;
     dec.reserve(n);
     for (int s = 0; s < n; ++s) dec.emplace_back(in[s], in_bytes[s], c->cfg.cdf_total);
@@ -1391,18 +1410,24 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
       std::vector<PassPlan> plans;
       if (!llm.empty()) plans = plan_catch_up(c, llm, upto);
       for (int k = 0; k < B; ++k) tg[k] = dec[order[k]].target();
-      Stage stg;
-      for (auto& p : plans) stage_pass(stg, p);
-      const size_t off_tg = stg.put(tg.data(), size_t(B) * 4);
-      const uint8_t* dst = upload_stage(c, stg);
-      for (auto& p : plans) run_pass(c, p, dst);
+      StepArgs A = step_args(c, B, true);
+      if (plans.empty() && B <= kRowsInline) {
+        // nothing to upload: the targets travel in the kernel arguments
+        A.targets = nullptr;
+        for (int k = 0; k < B; ++k) A.targets_in[k] = tg[k];
+      } else {
+        Stage stg;
+        for (auto& p : plans) stage_pass(stg, p);
+        const size_t off_tg = stg.put(tg.data(), size_t(B) * 4);
+        const uint8_t* dst = upload_stage(c, stg);
+        for (auto& p : plans) run_pass(c, p, dst);
+        A.targets = reinterpret_cast<const uint32_t*>(dst + off_tg);
+      }
       if (!llm.empty()) {
         run_lm_head(c, c->hlast.p, c->hinv.p, c->steprows.p, B, c->z.p);
         c->stats.llm_rows += llm.size();
       }
       c->stats.skipped += B - llm.size();
-      StepArgs A = step_args(c, B, true);
-      A.targets = reinterpret_cast<const uint32_t*>(dst + off_tg);
       A.lse = llm.empty() ? 0 : 1;  // every row skips the model: no logsumexp needed
       A.step_out = c->sout_hd;      // the outcome goes straight to host memory
       vocab_commit_step(c, A);
