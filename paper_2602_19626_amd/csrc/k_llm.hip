@@ -1187,14 +1187,16 @@ __device__ __forceinline__ void load_q(QFrag<PA>& q, const AttnArgs& a, const At
                                        int grp) {
   const int hd = a.hd;
   const long long qbase = ((long long)c.row * a.Hq + c.head) * hd;
+  // every load is issued (clamped into the row; c's row is valid even for an invalid column) and
+  // the entries outside are zeroed afterwards, so that no branch makes the loads' count
+  // path-dependent (a later wait would then drain every load in flight)
   if constexpr (PA == P_BF16) {
     const uint16_t* Q = static_cast<const uint16_t*>(a.q);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int k = s * 32 + grp * 8;
-      const v4i v = (c.valid && k < hd) ? *reinterpret_cast<const v4i*>(Q + qbase + k)
-                                        : v4i{0, 0, 0, 0};
-      q.b[s] = __builtin_bit_cast(v8bf, v);
+      const v4i v = *reinterpret_cast<const v4i*>(Q + qbase + min(k, hd - 8));
+      q.b[s] = __builtin_bit_cast(v8bf, (c.valid && k < hd) ? v : v4i{0, 0, 0, 0});
     }
   } else {
     // step s, lane group g: hd entry 16 g + s (the same mapping is used for K)
@@ -1202,10 +1204,9 @@ __device__ __forceinline__ void load_q(QFrag<PA>& q, const AttnArgs& a, const At
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd) {
       const int k = 16 * grp + 4 * qd;
-      const v4f v = (c.valid && k < hd) ? *reinterpret_cast<const v4f*>(Q + qbase + k)
-                                        : v4f{0.f, 0.f, 0.f, 0.f};
+      const v4f v = *reinterpret_cast<const v4f*>(Q + qbase + min(k, hd - 4));
 #pragma unroll
-      for (int e = 0; e < 4; ++e) q.f[4 * qd + e] = v[e];
+      for (int e = 0; e < 4; ++e) q.f[4 * qd + e] = (c.valid && k < hd) ? v[e] : 0.f;
     }
   }
 }
@@ -1264,22 +1265,26 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
     // K and V^T fragments of the 4 blocks, all loads in flight together
     v4i kf[4][2];
     v4i vf[HDMAX / 16][2];  // 16 keys per lane per hd block
+    // (loads clamped into range and masked afterwards, as for q)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const long long ks = sbase + (long long)slot_of(chunk_key(b, col)) * hd;
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int k = s * 32 + grp * 8;
-        kf[b][s] = k < hd ? *reinterpret_cast<const v4i*>(Kc + ks + k) : v4i{0, 0, 0, 0};
+        const v4i v = *reinterpret_cast<const v4i*>(Kc + ks + min(k, hd - 8));
+        kf[b][s] = k < hd ? v : v4i{0, 0, 0, 0};
       }
     }
 #pragma unroll
     for (int hb = 0; hb < HDMAX / 16; ++hb)
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        vf[hb][h] = hb < nhb ? *reinterpret_cast<const v4i*>(
-                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + vslot + 8 * h)
-                             : v4i{0, 0, 0, 0};
+      for (int h = 0; h < 2; ++h) {
+        const int hc = min(hb, nhb - 1);
+        const v4i v = *reinterpret_cast<const v4i*>(
+            Vt + sbase + (long long)(hc * 16 + col) * a.ring + vslot + 8 * h);
+        vf[hb][h] = hb < nhb ? v : v4i{0, 0, 0, 0};
+      }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       st[b] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1309,22 +1314,26 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
     const float* Vt = static_cast<const float*>(a.vt_cache);
     // every K and V^T fragment of the chunk requested before the first MFMA
     v4f kf[4][4], vf[HDMAX / 16][4];
+    // (loads clamped into range and masked afterwards, as for q)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const long long ks = sbase + (long long)slot_of(chunk_key(b, col)) * hd;
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
         const int k = 16 * grp + 4 * qd;
-        kf[b][qd] = k < hd ? *reinterpret_cast<const v4f*>(Kc + ks + k) : v4f{0.f, 0.f, 0.f, 0.f};
+        const v4f v = *reinterpret_cast<const v4f*>(Kc + ks + min(k, hd - 4));
+        kf[b][qd] = k < hd ? v : v4f{0.f, 0.f, 0.f, 0.f};
       }
     }
 #pragma unroll
     for (int hb = 0; hb < HDMAX / 16; ++hb)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        vf[hb][b] = hb < nhb ? *reinterpret_cast<const v4f*>(
-                                   Vt + sbase + (long long)(hb * 16 + col) * a.ring + vslot + 4 * b)
-                             : v4f{0.f, 0.f, 0.f, 0.f};
+      for (int b = 0; b < 4; ++b) {
+        const int hc = min(hb, nhb - 1);
+        const v4f v = *reinterpret_cast<const v4f*>(
+            Vt + sbase + (long long)(hc * 16 + col) * a.ring + vslot + 4 * b);
+        vf[hb][b] = hb < nhb ? v : v4f{0.f, 0.f, 0.f, 0.f};
+      }
     // the four blocks' MFMA chains interleaved step by step
 #pragma unroll
     for (int b = 0; b < 4; ++b) st[b] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1347,9 +1356,11 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
   return r;
 }
 
+// Column col of an item; a column past ncols is invalid and takes the last valid column's row,
+// head and position, so that every address derived from it stays inside the pass.
 __device__ __forceinline__ AttnCol attn_col(const AttnArgs& a, const AttnItem& it, int col) {
   const int g = a.Hq / a.Hk;
-  const int cc = it.c0 + col;
+  const int cc = it.c0 + min(col, it.ncols - 1);
   AttnCol c;
   c.valid = col < it.ncols;
   const int qo = cc / g;

@@ -553,7 +553,7 @@ __device__ __forceinline__ float ng_base(const StreamState& S, const NgRow& g, i
 }
 
 __device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& S,
-                                       const RowList& rows, NgPart* parts, int seg, int r,
+                                       const int32_t* rows, NgPart* parts, int seg, int r,
                                        int nseg, int tid, bool active, NgPart* wl) {
   const int lane = tid & 63, w = tid >> 6;
   const int V = P.V;
@@ -614,7 +614,7 @@ struct FixLds {
 
 // 256 threads (tid) of one row; active == false only passes the barriers
 __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& S,
-                                       const RowList& rows, const NgPart* parts, int nseg,
+                                       const int32_t* rows, const NgPart* parts, int nseg,
                                        StepOut* step_out, const Outcome* out, int r, int tid,
                                        bool active, FixLds& F, int pos_given) {
   const int nt = kSegThreads;
@@ -782,14 +782,14 @@ __global__ __launch_bounds__(64) void ngram_update_kernel(VocabParams P, StreamS
 }
 
 __global__ __launch_bounds__(kSegThreads) void ngram_dense_kernel(VocabParams P, StreamState S,
-                                                                  const RowList rows,
+                                                                  const int32_t* rows,
                                                                   NgPart* parts) {
   __shared__ NgPart wl[kSegWaves];
   v6_seg(P, S, rows, parts, blockIdx.x, blockIdx.y, gridDim.x, threadIdx.x, true, wl);
 }
 
 __global__ __launch_bounds__(kSegThreads) void ngram_fix_kernel(VocabParams P, StreamState S,
-                                                                const RowList rows,
+                                                                const int32_t* rows,
                                                                 const NgPart* parts, int nseg,
                                                                 StepOut* step_out,
                                                                 const Outcome* out, int pos) {
@@ -1022,7 +1022,7 @@ void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArg
   launch_ngram_update(P, S, A, s);
 }
 
-void launch_ngram_predict(const VocabParams& P, const StreamState& S, const RowList& rows, int B,
+void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
                           NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s,
                           int pos) {
   if (B <= 0) return;

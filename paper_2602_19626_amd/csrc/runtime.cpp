@@ -119,7 +119,6 @@ struct nc_ctx {
   DevBuf<float> z;
   DevBuf<float> zseg;  // encode: logits of a chunk of positions [pos][stream slot][V]
   DevBuf<int32_t> steprows, arows;
-  std::vector<int32_t> hsteprows;  // host copy of steprows
   DevBuf<uint32_t> targets;
   DevBuf<LsePart> lsep;
   DevBuf<SegPartial> segp;
@@ -369,7 +368,6 @@ void ensure_rows(nc_ctx* c, int rows) {
 void ensure_step(nc_ctx* c, int B) {
   const int nseg = int(ceil_div(c->V, kSeg));
   c->z.alloc((size_t)B * c->V);
-  if (size_t(B) > c->steprows.n) c->hsteprows.clear();  // a new device list starts undefined
   c->steprows.alloc(B);
   c->arows.alloc(B);
   c->targets.alloc(B);
@@ -787,22 +785,8 @@ bool ngram_on(const nc_ctx* c) {
   return (c->cfg.features & (NC_F_NGRAM | NC_F_ENSEMBLE)) != 0;
 }
 
-// The stream of each step row (device list plus its host copy).
-void set_steprows(nc_ctx* c, const int32_t* rows, size_t n) {
-  h2d(c, c->steprows.p, rows, n);
-  c->hsteprows.assign(rows, rows + n);
-}
-
-// Row list of a step over steprows[0..B); small steps carry the rows by value as well.
-RowList row_list(nc_ctx* c, int B) {
-  RowList r{};
-  r.p = c->steprows.p;
-  if (B <= kRowsInline && B <= int(c->hsteprows.size())) {
-    r.n_in = B;
-    for (int i = 0; i < B; ++i) r.v[i] = c->hsteprows[i];
-  }
-  return r;
-}
+// The stream of each step row.
+void set_steprows(nc_ctx* c, const int32_t* rows, size_t n) { h2d(c, c->steprows.p, rows, n); }
 
 void reset_streams(nc_ctx* c, int n, int maxT) {
   NC_CHECK(n >= 1 && n <= c->cfg.max_streams, NC_E_INVALID, "n_streams must be in [1, %d]",
@@ -865,7 +849,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
     std::vector<int32_t> ids(n);
     std::iota(ids.begin(), ids.end(), 0);
     set_steprows(c, ids.data(), ids.size());
-    launch_ngram_predict(c->vp, c->S, row_list(c, n), n, c->ngp.p, nullptr, nullptr, c->st);
+    launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
   }
   sync(c);
   c->hhist.assign(n, {});
@@ -875,7 +859,7 @@ void reset_streams(nc_ctx* c, int n, int maxT) {
 StepArgs step_args(nc_ctx* c, int B, bool decode) {
   StepArgs A{};
   A.B = B;
-  A.rows = row_list(c, B);
+  A.rows = c->steprows.p;
   A.z = c->z.p;
   A.decode = decode ? 1 : 0;
   A.targets = c->targets.p;
@@ -1266,7 +1250,7 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
     sync(c);
     set_steprows(c, order.data(), order.size());
     if (ngram_on(c))
-      launch_ngram_predict(c->vp, c->S, row_list(c, n), n, c->ngp.p, nullptr, nullptr, c->st);
+      launch_ngram_predict(c->vp, c->S, c->steprows.p, n, c->ngp.p, nullptr, nullptr, c->st);
     const int C = c->cfg.slide;
     // the n-gram chain of position i + 1 can run beside the distribution of position i when no
     // ensemble experts (P_1..P_K, single-buffered) are involved
@@ -1411,7 +1395,7 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
       if (!llm.empty()) plans = plan_catch_up(c, llm, upto);
       for (int k = 0; k < B; ++k) tg[k] = dec[order[k]].target();
       StepArgs A = step_args(c, B, true);
-      if (plans.empty() && B <= kRowsInline) {
+      if (plans.empty() && B <= kTargetsInline) {
         // nothing to upload: the targets travel in the kernel arguments
         A.targets = nullptr;
         for (int k = 0; k < B; ++k) A.targets_in[k] = tg[k];

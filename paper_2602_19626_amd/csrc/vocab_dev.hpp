@@ -77,27 +77,19 @@ struct VocabParams {
   float skip_bits, skip_pmax;
 };
 
-// Stream of each row of a step.  Up to kRowsInline rows are also carried by value in the kernel
-// arguments, so that a kernel of a small step reaches its stream's state without first waiting
-// for a load of the row list.
-constexpr int kRowsInline = 8;
-struct RowList {
-  const int32_t* p;  // [B] on the device
-  int n_in;          // rows held in v: B when B <= kRowsInline, else 0
-  int32_t v[kRowsInline];
-  __host__ __device__ int operator[](int r) const { return r < n_in ? v[r] : p[r]; }
-};
+// Decode steps of at most kTargetsInline rows pass their targets in the kernel arguments.
+constexpr int kTargetsInline = 8;
 
 // Rows of one step: row r is stream rows[r]; z row r of `z` (ld V) holds its logits when its mode
 // uses the LLM.  key[r] is the token (encode) or the target count (decode).
 struct StepArgs {
   int B;
-  RowList rows;
+  const int32_t* rows;
   const float* z;
   int decode;            // 0: key = token from hist at ncommit; 1: key = the row's target
   int no_update;         // 1: probe only (no bias update, no interval output)
-  const uint32_t* targets;            // decode: [B] on the device, or null: targets_in
-  uint32_t targets_in[kRowsInline];   // decode with targets == null: the targets of rows 0..B)
+  const uint32_t* targets;              // decode: [B] on the device, or null: targets_in
+  uint32_t targets_in[kTargetsInline];  // decode with targets == null: the targets of rows 0..B)
   LsePart* lse_parts;    // [B][nseg]
   void* seg_parts;       // SegPartial [B][nseg]
   NgPart* ng_parts;      // [B][nseg]
@@ -128,7 +120,7 @@ void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArg
 // n-gram distribution, entropy and mode of the current position of each row's stream; with
 // step_out, also packs the step's outcome and the next mode for the host (decode).
 // pos: the rows' position (>= 0, batched encode) or -1 (S.ncommit).
-void launch_ngram_predict(const VocabParams& P, const StreamState& S, const RowList& rows, int B,
+void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
                           NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s,
                           int pos = -1);
 // Only the step's distribution, interval and bias step (V1-V3, V4 for the ensemble), and only
