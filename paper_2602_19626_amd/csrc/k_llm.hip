@@ -1477,21 +1477,27 @@ __global__ __launch_bounds__(256) void attention_quad_kernel(const AttnArgs a) {
   state_put(a.ws + ((long long)item * MAXQ + qi) * QSTATE * 64, qs, lane);
 }
 
-// Few items, second kernel: quads -> groups -> output, one wave per item.  The (up to 4) quad
-// states of a group are loaded together before they are folded.
+// Few items, second kernel: quads -> groups -> output, one workgroup per item.  Wave w folds the
+// quads of the item's w-th group (their states loaded together) and leaves the group state in
+// LDS; wave 0 then folds the groups in order.  The folds are the sequential kernel's, in the same
+// order, so the output is the same.
+constexpr int FOLD_WAVES = (MAXQ + GQ - 2) / GQ + 1;  // groups an item may span
 template <int PO>
-__global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a) {
-  const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
+__global__ __launch_bounds__(64 * FOLD_WAVES) void attention_fold_kernel(const AttnArgs a) {
+  __shared__ float gst[FOLD_WAVES][QSTATE * 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const int item = blockIdx.x;
   const AttnItem it = a.items[item];
   const int nhb = a.hd / 16;
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);
   const int qlo = c_lo / QCH, qhi = c_hi / QCH;
+  const int gfirst = (qlo / GQ) * GQ;
+  const int ng = (qhi - gfirst) / GQ + 1;  // <= FOLD_WAVES: qhi - qlo < MAXQ
   const float* src = a.ws + (long long)item * MAXQ * QSTATE * 64;
-  ChunkState run, gs, p[GQ];
-  state_empty(run);
-  for (int g0 = (qlo / GQ) * GQ; g0 <= qhi; g0 += GQ) {
+  if (w < ng) {
+    const int g0 = gfirst + w * GQ;
+    ChunkState gs, p[GQ];
 #pragma unroll
     for (int u = 0; u < GQ; ++u)
       if (g0 + u >= qlo && g0 + u <= qhi) state_get(p[u], src + (g0 + u - qlo) * QSTATE * 64, lane);
@@ -1499,6 +1505,14 @@ __global__ __launch_bounds__(64) void attention_fold_kernel(const AttnArgs a) {
 #pragma unroll
     for (int u = 0; u < GQ; ++u)
       if (g0 + u >= qlo && g0 + u <= qhi) fold(gs, p[u], nhb);
+    state_put(gst[w], gs, lane);
+  }
+  __syncthreads();
+  if (w != 0) return;
+  ChunkState run, gs;
+  state_empty(run);
+  for (int k = 0; k < ng; ++k) {
+    state_get(gs, gst[k], lane);
     fold(run, gs, nhb);
   }
   float omax = attn_store<PO>(a, it, run, col, grp);
@@ -1728,7 +1742,8 @@ static void attn_go(const AttnArgs& a, bool parallel, hipStream_t s) {
   if (parallel) {
     const int nq = attention_quads(a.ctx_len);
     hipLaunchKernelGGL((attention_quad_kernel<PA>), dim3(a.n_items, nq), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64 * FOLD_WAVES), 0, s,
+                       a);
   } else {
     hipLaunchKernelGGL((attention_seq_kernel<PA, PO>), dim3((a.n_items + 3) / 4), dim3(256), 0, s,
                        a);
