@@ -527,17 +527,25 @@ struct NgRow {
   float inv_norm;     // 1 / (N + V)
 };
 
-// The row's n-gram weights: every order's context index is loaded first, then every count, so
-// the row costs two dependent loads rather than two per order.
+// The row's n-gram weights.  Lane q (mod kMaxOrder) of each wave fetches order q's context index
+// and then that context's total count, and every lane reads the four orders' values from those
+// lanes: two vector loads per row.  (Per-order scalar loads of the same values were issued one
+// after the other, each behind the previous one's wait.)  Must be called by whole waves.
 __device__ __forceinline__ NgRow ng_row(const VocabParams& P, const StreamState& S, int s) {
+  static_assert((kMaxOrder & (kMaxOrder - 1)) == 0, "kMaxOrder must be a power of two");
   NgRow g;
-#pragma unroll
-  for (int k = 0; k < kMaxOrder; ++k)
-    g.id[k] = k < P.K ? S.next_ctx[(size_t)s * kMaxOrder + k] : -1;
+  const int q = threadIdx.x & (kMaxOrder - 1);
+  const int raw = S.next_ctx[(size_t)s * kMaxOrder + q];
   const int seen = S.nseen[s];
+  const int idq = q < P.K ? raw : -1;
+  // (indices clamped into the tables; a missing context's count is masked)
+  const int nraw = S.pool_sum[((size_t)s * P.K + min(q, P.K - 1)) * S.maxctx + max(idq, 0)];
+  const int nq = idq >= 0 ? nraw : 0;
 #pragma unroll
-  for (int k = 0; k < kMaxOrder; ++k)
-    g.n[k] = g.id[k] >= 0 ? S.pool_sum[((size_t)s * P.K + k) * S.maxctx + g.id[k]] : 0;
+  for (int k = 0; k < kMaxOrder; ++k) {
+    g.id[k] = __shfl(idq, k, 64);
+    g.n[k] = __shfl(nq, k, 64);
+  }
 #pragma unroll
   for (int k = 0; k < kMaxOrder; ++k) {
     g.present[k] = g.n[k] > 0 ? 1 : 0;
