@@ -249,22 +249,28 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
                                        bool active, SegLds& L, int* s_sym) {
   const int V = P.V;
   const int s = A.rows[r];
-  if (active && tid < nseg)
-    L.parts[tid] = static_cast<const SegPartial*>(A.seg_parts)[(size_t)r * nseg + tid];
-  if (tid == 0) *s_sym = -1;
-  // the key (decode: the host's target; encode: the token at the stream's next position) is
-  // fetched with the row, not after the scan
-  const int i_pos = !active ? 0 : (A.pos >= 0 ? A.pos : S.ncommit[s]);
-  const uint32_t key =
-      !active ? 0u
-              : (A.decode ? (A.targets ? A.targets[r] : A.targets_in[r])
-                          : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
+  // Issue order: the count partials of the row's segments (into registers; an LDS store right
+  // after the load would wait for it before anything else is issued), the row's vectors and
+  // metadata, then the key (decode: the host's target; encode: the token at the stream's next
+  // position, behind the committed count), all before the scan needs any of them.
+  SegPartial part{};
+  if (active)
+    part = static_cast<const SegPartial*>(A.seg_parts)[(size_t)r * nseg + min(tid, nseg - 1)];
   RowIn R;
   RowVec v;
   float p[4][4], pt[4][4];
   if (active) {
     row_fetch(P, S, A, r, s, seg, tid, v);
     R = make_row(P, S, A, r, s, nseg);
+  }
+  const int i_pos = !active ? 0 : (A.pos >= 0 ? A.pos : S.ncommit[s]);
+  const uint32_t key =
+      !active ? 0u
+              : (A.decode ? (A.targets ? A.targets[r] : A.targets_in[r])
+                          : uint32_t(S.hist[(size_t)s * S.maxT + i_pos]));
+  if (active && tid < nseg) L.parts[tid] = part;
+  if (tid == 0) *s_sym = -1;
+  if (active) {
     row_probs(R, v, seg, tid, p, pt);
   } else {
 #pragma unroll
