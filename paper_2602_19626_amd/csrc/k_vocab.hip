@@ -489,8 +489,24 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
       } else {
         int32_t* sl = S.pool + (t * S.maxctx + id) * kSlots * 2;
         const int n = S.pool_n[t * S.maxctx + id];
-        int j = 0;
-        while (j < n && sl[2 * j] != sym) ++j;
+        // first slot holding t*, or n: eight slots per round of loads rather than one dependent
+        // load per slot (kSlots is a multiple of 8, so a round stays inside the pool)
+        static_assert(kSlots % 8 == 0, "slot rounds of eight");
+        int j = n;
+        for (int j0 = 0; j0 < n; j0 += 8) {
+          typedef int32_t i4 __attribute__((ext_vector_type(4)));
+          const i4* q4 = reinterpret_cast<const i4*>(sl + 2 * j0);
+          const i4 a0 = q4[0], a1 = q4[1], a2 = q4[2], a3 = q4[3];
+          const int32_t tk[8] = {a0.x, a0.z, a1.x, a1.z, a2.x, a2.z, a3.x, a3.z};
+          int hit = -1;
+#pragma unroll
+          for (int u = 7; u >= 0; --u)
+            if (j0 + u < n && tk[u] == sym) hit = j0 + u;
+          if (hit >= 0) {
+            j = hit;
+            break;
+          }
+        }
         if (j < n) {
           sl[2 * j + 1] += 1;
           S.pool_sum[t * S.maxctx + id] += 1;
