@@ -204,6 +204,39 @@ __device__ __forceinline__ void row_fetch(const VocabParams& P, const StreamStat
 __device__ __forceinline__ void row_probs(const RowIn& R, const RowVec& v, uint32_t seg, int tid,
                                           float (&p)[4][4], float (&pt)[4][4]) {
   const bool llm = R.mode != M_SKIP, ng = R.mode != M_LLM, hb = R.use_head && llm;
+  if (R.mode == M_ENS) {
+    // The ensemble also reads P_1..P_K at the thread's 16 entries: every vector is requested
+    // (clamped into the row, masked after) before the first is used, rather than one dependent
+    // load per entry and order.  The arithmetic is row_prob_v's, in its order.
+    f4v pk[4][kMaxOrder];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t0 = seg_index(seg, j, tid, 0);
+      const uint32_t tc = t0 < uint32_t(R.V) ? t0 : 0u;
+#pragma unroll
+      for (int k = 0; k < kMaxOrder; ++k)
+        pk[j][k] = *reinterpret_cast<const f4v*>(R.pk + (size_t)min(k, R.K - 1) * R.V + tc);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t0 = seg_index(seg, j, tid, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (t0 >= uint32_t(R.V)) {
+          p[j][i] = pt[j][i] = 0.f;
+          continue;
+        }
+        const float q = expf((R.use_head ? v.z[j][i] + v.b[j][i] : v.z[j][i]) - R.lse);
+        pt[j][i] = q;
+        float pv = R.w[0] * q;
+#pragma unroll
+        for (int k = 1; k <= kMaxOrder; ++k)
+          if (k <= R.K) pv = pv + R.w[k] * pk[j][k - 1][i];
+        p[j][i] = pv;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const uint32_t t0 = seg_index(seg, j, tid, 0);
