@@ -949,7 +949,8 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
       pre[k] = a.ssq[(long long)ar * nb16 + (i - m * nb16)];
     }
   }
-  if constexpr (EPI != E_STORE) load_w(real ? wave : 0, 0, real);
+  // (the residual GEMMs, whose waves may own two parts, request both at the top of their loop)
+  if constexpr (EPI != E_STORE && NBUF == 1) load_w(real ? wave : 0, 0, real);
   // The inputs of this thread's first epilogue item are fetched now as well: the row metadata of
   // a q/k/v output (its RoPE entry follows once the metadata is in), or the residual value and
   // gain of a residual output.
@@ -965,7 +966,7 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
     pre_x = *xp;
     pre_g = *(a.y_out ? a.y_gain + n : xp);  // (unused without y_out)
   }
-  load_a(real ? wave : 0, 0, real);
+  if constexpr (NBUF == 1) load_a(real ? wave : 0, 0, real);
   if constexpr (AM == A_NORM) {
     // only wave 0 uses it (and only with given scales); the other waves read the start of a
     // weight row they load anyway rather than all hitting one line
@@ -1023,8 +1024,10 @@ __global__ __launch_bounds__(64 * SPLIT_WAVES) void gemm_split_kernel(const Gemm
   };
   // parts wave, wave + nw, ...
   if constexpr (NBUF == 2) {
+    // both parts' loads go out before either is consumed (a first part loaded ahead of the loop
+    // would be waited for before the second part's loads were issued)
     for (int s = wave; s < S; s += 2 * nw) {
-      if (s != wave) load_part(s, 0);
+      load_part(s, 0);
       if (s + nw < S) load_part(s + nw, NBUF - 1);
       compute_part(s, 0);
       if (s + nw < S) compute_part(s + nw, NBUF - 1);
