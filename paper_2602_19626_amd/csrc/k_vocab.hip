@@ -75,22 +75,29 @@ __device__ __forceinline__ float row_prob_v(const RowIn& R, int t, float z, floa
 // Mixture / gate weights of a stream: mixer w = exp(log w); ensemble w = softmax(theta).
 __device__ __forceinline__ void row_weights(const VocabParams& P, const float* lw, float* w) {
   if (P.ensemble) {
-    // loops unrolled to the compile-time bound (n <= kMaxOrder + 1) so that w stays in registers
+    // every one of the kMaxOrder + 1 slots is read and written unconditionally (entries past n
+    // masked by selects), so that w stays in registers; the kept terms are combined in order
     const int n = P.K + 1;
-    float mx = lw[0];
+    float l[kMaxOrder + 1];
 #pragma unroll
-    for (int j = 1; j <= kMaxOrder; ++j)
-      if (j < n) mx = fmaxf(mx, lw[j]);
+    for (int j = 0; j <= kMaxOrder; ++j) l[j] = lw[j];
+    float mx = l[0];
+#pragma unroll
+    for (int j = 1; j <= kMaxOrder; ++j) mx = j < n ? fmaxf(mx, l[j]) : mx;
     float s = 0.f;
 #pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j)
-      if (j < n) s += expf(lw[j] - mx);
+    for (int j = 0; j <= kMaxOrder; ++j) {
+      const float e = expf(l[j] - mx);
+      s = j < n ? s + e : s;
+    }
 #pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j)
-      if (j < n) w[j] = expf(lw[j] - mx) / s;
+    for (int j = 0; j <= kMaxOrder; ++j) w[j] = j < n ? expf(l[j] - mx) / s : 0.f;
   } else {
+    // (the same slots written as by the ensemble branch, so that the two merge by value)
     w[0] = expf(lw[0]);
     w[1] = expf(lw[1]);
+#pragma unroll
+    for (int j = 2; j <= kMaxOrder; ++j) w[j] = 0.f;
   }
 }
 
@@ -642,7 +649,11 @@ __device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& 
       for (int i = 0; i < 4; ++i) {
         const uint32_t t = t0 + i;
         float pv = float(u[j][i] + 1) * g.inv_norm;  // ng_base
-        for (int k = 1; k <= P.K; ++k) {
+        // orders unrolled to the compile-time bound: with a runtime trip count the row weights
+        // were indexed dynamically and kept in LDS, two LDS round trips per entry and order
+#pragma unroll
+        for (int k = 1; k <= kMaxOrder; ++k) {
+          if (k > P.K) break;
           if (g.present[k - 1]) pv = (1.0f - g.lam[k - 1]) * pv;
           if (S.pk) S.pk[((size_t)s * P.K + (k - 1)) * V + t] = pv;
         }
