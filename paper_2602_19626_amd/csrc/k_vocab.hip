@@ -617,11 +617,6 @@ __device__ __forceinline__ NgRow ng_row(const VocabParams& P, const StreamState&
   return g;
 }
 
-__device__ __forceinline__ float ng_base(const StreamState& S, const NgRow& g, int s, int V,
-                                         int t) {
-  return float(S.uni[(size_t)s * V + t] + 1) * g.inv_norm;
-}
-
 __device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& S,
                                        const int32_t* rows, NgPart* parts, int seg, int r,
                                        int nseg, int tid, bool active, NgPart* wl) {
@@ -648,7 +643,7 @@ __device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t t = t0 + i;
-        float pv = float(u[j][i] + 1) * g.inv_norm;  // ng_base
+        float pv = float(u[j][i] + 1) * g.inv_norm;  // unigram base (n_t + 1) / (N + V)
         // orders unrolled to the compile-time bound: with a runtime trip count the row weights
         // were indexed dynamically and kept in LDS, two LDS round trips per entry and order
 #pragma unroll
@@ -681,10 +676,27 @@ __device__ __forceinline__ void v6_seg(const VocabParams& P, const StreamState& 
 
 // ---- V7: sparse n-gram entries, entropy, skip decision ---------------------------------------
 
-struct FixLds {
+struct alignas(16) FixLds {
   int lt[kMaxOrder][kSlots], lc[kMaxOrder][kSlots], ln[kMaxOrder];
   float sh[kSegThreads], smx[kSegThreads];
 };
+
+// The last of the first ln slots of order row q holding tok, or -1 (a pool holds a token at most
+// once, so it is also the first); four slots per LDS read.
+__device__ __forceinline__ int slot_last(const FixLds& F, int q, int ln, int tok) {
+  static_assert(kSlots % 4 == 0, "slot rows are read four at a time");
+  typedef int32_t i4 __attribute__((ext_vector_type(4)));
+  const i4* row = reinterpret_cast<const i4*>(F.lt[q]);
+  int at = -1;
+  for (int j0 = 0; j0 < ln; j0 += 4) {
+    const i4 v = row[j0 >> 2];
+    if (v.x == tok) at = j0;
+    if (v.y == tok && j0 + 1 < ln) at = j0 + 1;
+    if (v.z == tok && j0 + 2 < ln) at = j0 + 2;
+    if (v.w == tok && j0 + 3 < ln) at = j0 + 3;
+  }
+  return at;
+}
 
 // 256 threads (tid) of one row; active == false only passes the barriers
 __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& S,
@@ -743,29 +755,25 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
       const int k = e / kSlots + 1, j = e % kSlots;
       if (j >= F.ln[k - 1]) continue;
       const int tok = F.lt[k - 1][j];
+      // the entry's unigram count and current p_ng are requested before the slot scans
+      const int32_t u_tok = S.uni[(size_t)s * V + tok];
+      const float old = S.png[(size_t)s * V + tok];
       bool owner = true;  // first occurrence over (order, slot) in increasing order
-      for (int k2 = 1; k2 < k && owner; ++k2)
-        for (int j2 = 0; j2 < F.ln[k2 - 1]; ++j2)
-          if (F.lt[k2 - 1][j2] == tok) {
-            owner = false;
-            break;
-          }
+      for (int k2 = 1; k2 < k && owner; ++k2) owner = slot_last(F, k2 - 1, F.ln[k2 - 1], tok) < 0;
       if (!owner) continue;
       // P_k(tok) = lambda_k Phat_k(tok) + (1 - lambda_k) P_{k-1}(tok), k = 1..K (section 3.5)
-      float pv = ng_base(S, g, s, V, tok);
+      float pv = float(u_tok + 1) * g.inv_norm;  // unigram base (n_t + 1) / (N + V)
 #pragma unroll
       for (int k2 = 1; k2 <= kMaxOrder; ++k2) {
         if (k2 > P.K) break;
         if (g.present[k2 - 1]) {
-          int cnt = 0;
-          for (int j2 = 0; j2 < F.ln[k2 - 1]; ++j2)
-            if (F.lt[k2 - 1][j2] == tok) cnt = F.lc[k2 - 1][j2];
+          const int at = slot_last(F, k2 - 1, F.ln[k2 - 1], tok);
+          const int cnt = at >= 0 ? F.lc[k2 - 1][at] : 0;
           const float n = float(g.n[k2 - 1]);
           pv = g.lam[k2 - 1] * (float(cnt) / n) + (1.0f - g.lam[k2 - 1]) * pv;
         }
         if (S.pk) S.pk[((size_t)s * P.K + (k2 - 1)) * V + tok] = pv;
       }
-      const float old = S.png[(size_t)s * V + tok];
       S.png[(size_t)s * V + tok] = pv;
       dh = dh + (old * log2f(old) - pv * log2f(pv));
       dmx = fmaxf(dmx, pv);
