@@ -164,6 +164,7 @@ __device__ __forceinline__ SegPartial seg_reduce(const float (&p)[4][4], uint32_
 
 // Second pass, row part: combine the row's partials (in LDS) in segment order into the residual,
 // the argmax and this segment's starting CDF value.
+// parts: kMaxSegs entries (in LDS), the first nseg of them the row's partials.
 __device__ __forceinline__ RowQuant seg_combine(const SegPartial* parts, uint32_t nseg,
                                                 uint32_t seg, uint32_t V, uint32_t total) {
   RowQuant q;
@@ -172,12 +173,23 @@ __device__ __forceinline__ RowQuant seg_combine(const SegPartial* parts, uint32_
   float bv = -1.f;
   uint32_t bi = 0xFFFFFFFFu;
   int bad = 0;
-  for (uint32_t k = 0; k < nseg; ++k) {
-    const SegPartial s = parts[k];
-    if (k < seg) before += s.sum;
-    tot += s.sum;
-    argmax_merge(bv, bi, s.maxv, s.maxi);
-    bad |= s.bad;
+  // partials read sixteen at a time (parts holds kMaxSegs entries, so every read is in range)
+  // and combined in segment order
+  for (uint32_t k0 = 0; k0 < nseg; k0 += 16) {
+    SegPartial buf[16];
+#pragma unroll
+    for (uint32_t u = 0; u < 16; ++u) buf[u] = parts[k0 + u];
+#pragma unroll
+    for (uint32_t u = 0; u < 16; ++u) {
+      const uint32_t k = k0 + u;
+      if (k < nseg) {
+        const SegPartial& s = buf[u];
+        if (k < seg) before += s.sum;
+        tot += s.sum;
+        argmax_merge(bv, bi, s.maxv, s.maxi);
+        bad |= s.bad;
+      }
+    }
   }
   const int64_t r = int64_t(total) - int64_t(tot);
   q.argmax = bi;
