@@ -29,13 +29,14 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t exact_floor_scaled(float p, uint32_t m) {
   const uint32_t bits = __float_as_uint(p);
   const uint32_t e = (bits >> 23) & 0xFFu;
-  if (e == 0) return 0;  // zero or subnormal: p * m < 2^-126 * 2^24 < 1
   const uint64_t mant = (bits & 0x7FFFFFu) | 0x800000u;  // p = mant * 2^(e - 150)
   const int sh = 150 - int(e);
-  if (sh >= 64) return 0;
   // both factors are below 2^24 (the mask states it for m, which the callers' total <= 2^24
   // bounds), so the product is two full-rate 24-bit multiplies rather than a 64-bit one
-  return uint32_t((mant * uint64_t(m & 0xFFFFFFu)) >> sh);  // p <= 1 => sh >= 23, < 2^48
+  const uint32_t r = uint32_t((mant * uint64_t(m & 0xFFFFFFu)) >> (sh & 63));  // p <= 1: sh >= 23
+  // zero or subnormal (p * m < 2^-126 * 2^24 < 1) and shifts of 64 or more give 0; selects
+  // rather than branches, as this runs for every entry of a row
+  return (e == 0 || sh >= 64) ? 0u : r;
 }
 
 __device__ __forceinline__ uint32_t floor_count(float p, uint32_t m) {
@@ -202,10 +203,11 @@ __device__ __forceinline__ RowQuant seg_combine(const SegPartial* parts, uint32_
 }
 
 // Second pass, segment part: exclusive scan of the corrected counts of this segment.  On return
-// base[j] = cdf[seg_index(seg, j, tid, 0)], so cdf[idx + 1] = base[j] + c'_{j,0} + ... + c'_{j,i}.
+// base[j] = cdf[seg_index(seg, j, tid, 0)] and c[j][i] is the corrected count of entry (j, i)
+// (0 at or beyond V), so cdf[idx + 1] = base[j] + c[j][0] + ... + c[j][i].
 __device__ __forceinline__ void seg_scan(const float (&p)[4][4], uint32_t seg, uint32_t V,
-                                         const RowQuant& q, uint32_t (&base)[4], SegLds& L,
-                                         int tid) {
+                                         const RowQuant& q, uint32_t (&base)[4],
+                                         uint32_t (&c)[4][4], SegLds& L, int tid) {
   const int lane = tid & 63, w = tid >> 6;
   uint32_t excl[4];
 #pragma unroll
@@ -214,7 +216,8 @@ __device__ __forceinline__ void seg_scan(const float (&p)[4][4], uint32_t seg, u
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t idx = seg_index(seg, j, tid, i);
-      if (idx < V) s += corrected_count(p[j][i], idx, q);
+      c[j][i] = idx < V ? corrected_count(p[j][i], idx, q) : 0u;
+      s += c[j][i];
     }
     uint32_t v = s;
 #pragma unroll

@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_scan_kernel(
   load_seg<kVec4, true>(probs + size_t(row) * V, seg, V, v);
   __syncthreads();
   const RowQuant q = seg_combine(L.parts, nseg, seg, V, total);
-  uint32_t base[4];
-  seg_scan(v, seg, V, q, base, L, tid);
+  uint32_t base[4], cnt[4][4];
+  seg_scan(v, seg, V, q, base, cnt, L, tid);
   uint32_t* out = cdf + size_t(row) * (size_t(V) + 1);
   if (seg == 0 && tid == 0) {
     out[0] = 0;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_scan_kernel(
     for (int i = 0; i < 4; ++i) {
       const uint32_t idx = seg_index(seg, j, tid, i);
       if (idx < V) {
-        run += corrected_count(v[j][i], idx, q);
+        run += cnt[j][i];
         __builtin_nontemporal_store(run, out + idx + 1);
       }
     }

@@ -321,33 +321,44 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
   __syncthreads();
   RowQuant q{};
   if (active) q = seg_combine(L.parts, nseg, seg, V, P.total);
-  uint32_t base[4];
-  seg_scan(p, seg, V, q, base, L, tid);
+  uint32_t base[4], cnt[4][4];
+  seg_scan(p, seg, V, q, base, cnt, L, tid);
   int found = -1;
   uint32_t fcl = 0, fch = 0;
   float fp = 0.f, fpt = 0.f, fpng = 0.f;
   if (active) {
+    // the entry whose interval holds the key (decode) or the key's entry (encode), by selects
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       uint32_t run = base[j];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t t = seg_index(seg, j, tid, i);
-        if (t < uint32_t(V)) {
-          const uint32_t c = corrected_count(p[j][i], t, q);
-          const bool hit = A.decode ? (key >= run && key - run < c) : (t == key);
-          if (hit) {
-            found = int(t);
-            fcl = run;
-            fch = run + c;
-            fp = p[j][i];
-            fpt = pt[j][i];
-            fpng = v.g[j][i];  // the row's p_ng at t, fetched with the row
-          }
-          if (A.dbg_cdf) A.dbg_cdf[(size_t)r * (V + 1) + t + 1] = run + c;
+        const uint32_t c = cnt[j][i];
+        const bool hit = t < uint32_t(V) &&
+                         (A.decode ? (key >= run && key - run < c) : (t == key));
+        found = hit ? int(t) : found;
+        fcl = hit ? run : fcl;
+        fch = hit ? run + c : fch;
+        fp = hit ? p[j][i] : fp;
+        fpt = hit ? pt[j][i] : fpt;
+        fpng = hit ? v.g[j][i] : fpng;  // the row's p_ng at t, fetched with the row
+        run += c;
+      }
+    }
+    // full-row diagnostics (single-row probes)
+    if (A.dbg_cdf || A.dbg_p || A.dbg_pt) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        uint32_t run = base[j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t t = seg_index(seg, j, tid, i);
+          run += cnt[j][i];
+          if (t >= uint32_t(V)) continue;
+          if (A.dbg_cdf) A.dbg_cdf[(size_t)r * (V + 1) + t + 1] = run;
           if (A.dbg_p) A.dbg_p[(size_t)r * V + t] = p[j][i];
           if (A.dbg_pt) A.dbg_pt[(size_t)r * V + t] = pt[j][i];
-          run += c;
         }
       }
     }
