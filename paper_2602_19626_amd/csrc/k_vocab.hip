@@ -447,30 +447,46 @@ __device__ __forceinline__ void v4_seg(const VocabParams& P, const StreamState& 
 
 // ---- V5: n-gram + mixer / gate update with the coded symbol --------------------------------
 
-__device__ __forceinline__ uint32_t ctx_hash(const int32_t* toks, int k) {
+// A context of up to kMaxOrder tokens.  Held by value and walked by loops unrolled to the
+// compile-time bound (with the order k as a guard), so that it stays in registers.
+struct Ctx {
+  int32_t v[kMaxOrder];
+};
+
+__device__ __forceinline__ uint32_t ctx_hash(const Ctx& c, int k) {
   uint64_t h = 0x9E3779B97F4A7C15ull * uint64_t(k + 1);
-  for (int i = 0; i < k; ++i) {
-    h ^= uint64_t(uint32_t(toks[i])) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
-    h *= 0xBF58476D1CE4E5B9ull;
-  }
+#pragma unroll
+  for (int i = 0; i < kMaxOrder; ++i)
+    if (i < k) {
+      h ^= uint64_t(uint32_t(c.v[i])) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+      h *= 0xBF58476D1CE4E5B9ull;
+    }
   h ^= h >> 31;
   return uint32_t(h);
 }
 
-// Probe the order-k table t for the context toks[0..k); returns the pool index or -1, and the
+// Probe the order-k table t for the context c.v[0..k); returns the pool index or -1, and the
 // empty table slot where it would go in *ins.
-__device__ int ctx_find(const StreamState& S, size_t t, const int32_t* toks, int k, int* ins) {
-  const int32_t* keys = S.keys + t * S.cap * 4;
+__device__ __forceinline__ int ctx_find(const StreamState& S, size_t t, const Ctx& c, int k,
+                                         int* ins) {
+  typedef int32_t i4 __attribute__((ext_vector_type(4)));
+  static_assert(kMaxOrder == 4, "a table key is one 16-byte vector");
+  const i4* keys = reinterpret_cast<const i4*>(S.keys + t * S.cap * 4);
   const int32_t* kidx = S.kidx + t * S.cap;
-  uint32_t h = ctx_hash(toks, k) & uint32_t(S.cap - 1);
+  uint32_t h = ctx_hash(c, k) & uint32_t(S.cap - 1);
   for (int probe = 0; probe < S.cap; ++probe) {
+    // the slot's pool index and key are requested together (the key is read whether or not the
+    // slot is in use)
     const int id = kidx[h];
+    const i4 kk = keys[h];
+    bool eq = true;
+#pragma unroll
+    for (int i = 0; i < kMaxOrder; ++i)
+      if (i < k) eq = eq && kk[i] == c.v[i];
     if (id < 0) {
       *ins = int(h);
       return -1;
     }
-    bool eq = true;
-    for (int i = 0; i < k; ++i) eq = eq && keys[(size_t)h * 4 + i] == toks[i];
     if (eq) return id;
     h = (h + 1) & uint32_t(S.cap - 1);
   }
@@ -520,16 +536,19 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
   }
   if (on && counts && (P.use_ngram || P.ensemble) && k >= 1 && k <= P.K) {
     const size_t t = (size_t)s * P.K + (k - 1);
-    int32_t ctx[kMaxOrder];
+    Ctx ctx{};
     // insert t* as a continuation of the order-k context ending at t_{i-1}
     if (i >= k) {
-      for (int q = 0; q < k; ++q) ctx[q] = hist[i - k + q];
+#pragma unroll
+      for (int q = 0; q < kMaxOrder; ++q)
+        if (q < k) ctx.v[q] = hist[i - k + q];
       int ins = -1;
       int id = ctx_find(S, t, ctx, k, &ins);
       if (id < 0) {
         if (ins >= 0 && S.nctx[t] < min(S.maxctx, P.ngram_max_contexts)) {
           id = S.nctx[t]++;
-          for (int q = 0; q < 4; ++q) S.keys[(t * S.cap + ins) * 4 + q] = q < k ? ctx[q] : -1;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) S.keys[(t * S.cap + ins) * 4 + q] = q < k ? ctx.v[q] : -1;
           S.kidx[t * S.cap + ins] = id;
           int32_t* sl = S.pool + (t * S.maxctx + id) * kSlots * 2;
           sl[0] = sym;
@@ -579,8 +598,11 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
     // context of the next position: t_{i-k+1} .. t_i (= t*)
     int nid = -1;
     if (i + 1 >= k) {
-      for (int q = 0; q < k - 1; ++q) ctx[q] = hist[i - k + 1 + q];
-      ctx[k - 1] = sym;
+#pragma unroll
+      for (int q = 0; q < kMaxOrder; ++q) {
+        if (q < k - 1) ctx.v[q] = hist[i - k + 1 + q];
+        if (q == k - 1) ctx.v[q] = sym;
+      }
       int ins;
       nid = ctx_find(S, t, ctx, k, &ins);
     }
