@@ -54,24 +54,6 @@ struct RowIn {
   float w[kMaxExperts];
 };
 
-// Coding probability of entry t from its logit z, bias b and n-gram probability g; *pt receives
-// the bias-head probability softmax(z + b)_t.
-__device__ __forceinline__ float row_prob_v(const RowIn& R, int t, float z, float b, float g,
-                                            float* pt) {
-  float q = 0.f;
-  if (R.mode != M_SKIP) q = expf((R.use_head ? z + b : z) - R.lse);
-  *pt = q;
-  if (R.mode == M_LLM) return q;
-  if (R.mode == M_SKIP) return g;
-  if (R.mode == M_MIX) return R.w[0] * q + R.w[1] * g;
-  float p = R.w[0] * q;
-  // orders unrolled to the compile-time bound so that w stays in registers
-#pragma unroll
-  for (int j = 1; j <= kMaxOrder; ++j)
-    if (j <= R.K) p = p + R.w[j] * R.pk[(size_t)(j - 1) * R.V + t];
-  return p;
-}
-
 // Mixture / gate weights of a stream: mixer w = exp(log w); ensemble w = softmax(theta).
 __device__ __forceinline__ void row_weights(const VocabParams& P, const float* lw, float* w) {
   if (P.ensemble) {
@@ -210,11 +192,10 @@ __device__ __forceinline__ void row_fetch(const VocabParams& P, const StreamStat
 // beyond V.
 __device__ __forceinline__ void row_probs(const RowIn& R, const RowVec& v, uint32_t seg, int tid,
                                           float (&p)[4][4], float (&pt)[4][4]) {
-  const bool llm = R.mode != M_SKIP, ng = R.mode != M_LLM, hb = R.use_head && llm;
   if (R.mode == M_ENS) {
     // The ensemble also reads P_1..P_K at the thread's 16 entries: every vector is requested
     // (clamped into the row, masked after) before the first is used, rather than one dependent
-    // load per entry and order.  The arithmetic is row_prob_v's, in its order.
+    // load per entry and order.  p = w0 q + w1 P_1 + ... + wK P_K, added in that order.
     f4v pk[4][kMaxOrder];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -244,17 +225,30 @@ __device__ __forceinline__ void row_probs(const RowIn& R, const RowVec& v, uint3
     }
     return;
   }
+  // The other forms, one loop per form (the mode is the row's, uniform over the workgroup):
+  // SKIP p = g; LLM p = q; MIX p = w0 q + w1 g; with q = exp(z (+ b) - lse) the bias-head
+  // probability, returned in pt (0 for SKIP).
+  if (R.mode == M_SKIP) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool in = seg_index(seg, j, tid, 0) < uint32_t(R.V);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        p[j][i] = in ? v.g[j][i] : 0.f;
+        pt[j][i] = 0.f;
+      }
+    }
+    return;
+  }
+  const bool mix = R.mode == M_MIX;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint32_t t0 = seg_index(seg, j, tid, 0);
-    if (t0 < uint32_t(R.V)) {
+    const bool in = seg_index(seg, j, tid, 0) < uint32_t(R.V);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        p[j][i] = row_prob_v(R, int(t0) + i, llm ? v.z[j][i] : 0.f, hb ? v.b[j][i] : 0.f,
-                             ng ? v.g[j][i] : 0.f, &pt[j][i]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) p[j][i] = pt[j][i] = 0.f;
+    for (int i = 0; i < 4; ++i) {
+      const float q = expf((R.use_head ? v.z[j][i] + v.b[j][i] : v.z[j][i]) - R.lse);
+      pt[j][i] = in ? q : 0.f;
+      p[j][i] = in ? (mix ? R.w[0] * q + R.w[1] * v.g[j][i] : q) : 0.f;
     }
   }
 }
