@@ -196,7 +196,7 @@ def main():
     ap.add_argument("--kernel", default="attn", help="kernel class for the roofline")
     ap.add_argument("--max-len", type=int, default=None, help="truncate streams (quick runs)")
     ap.add_argument("--n-streams", type=int, default=None)
-    ap.add_argument("--cpu-sample", type=int, default=250)
+    ap.add_argument("--cpu-sample", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain streaming kernel of this size first (counter scaling)")
