@@ -1,7 +1,10 @@
-"""Host-side logic of bench.py: the counter-file reduction behind the roofline's traffic figure."""
+"""Host-side logic of bench.py: the counter-file reduction behind the roofline's traffic figure
+and the one-GPU rule."""
 import csv
 import json
 import os
+import subprocess
+import sys
 
 import bench
 
@@ -58,3 +61,13 @@ def test_traffic_from_counts_class_launches(tmp_path, monkeypatch):
     assert t["launches"] == 3
     assert t["fetch_bytes_per_launch"] == round(500 * 1024 / 3)
     assert t["write_bytes_per_launch"] == round(9 * 1024 / 3)
+
+
+def test_more_than_one_gpu_is_refused():
+    """`--gpus N` with N > 1 exits with status 2 and a message, before any device work."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
