@@ -98,8 +98,9 @@ def traffic_from(fetch_csv: str, write_csv: str, kernel: str, workload: str, pro
 
 
 def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024), reps: int = 20):
-    """nc_quantize_cdf24 alone (two kernels: segment reduce, segment scan) on float32 rows of
-    softmax-shaped probabilities; algorithmic bytes per row = read 4V + write 4(V + 1)."""
+    """nc_quantize_cdf24 alone on float32 rows of softmax-shaped probabilities (up to 64 rows the
+    segment reduce + scan kernels, more rows the one-workgroup-per-row kernel); algorithmic bytes
+    per row = read 4V + write 4(V + 1)."""
     out = []
     g = torch.Generator(device="cuda").manual_seed(5)
     for rows in rows_list:

@@ -89,6 +89,7 @@ constexpr int kRowWaves = kRowThreads / 64;
 constexpr int kRowBlocks = 16;
 constexpr int kRowBlock = kRowThreads * 4;  // 3072 entries
 constexpr uint32_t kRowMaxV = kRowBlocks * kRowBlock;
+constexpr uint32_t kSegPathMaxRows = 64;
 
 __device__ __forceinline__ void row_load4(const float* p, uint32_t i0, uint32_t V, float (&x)[4]) {
   if (i0 + 3 < V) {
@@ -261,7 +262,10 @@ void launch_quantize_cdf(const float* p, uint32_t rows, uint32_t V, uint32_t tot
                          int32_t* status, void* workspace, hipStream_t s) {
   if (rows == 0) return;
   const bool vec = (V % 4 == 0) && (reinterpret_cast<uintptr_t>(p) % 16 == 0);
-  if (vec && V <= kRowMaxV) {
+  // The row kernel places one workgroup per row, so a few rows leave most CUs idle; up to
+  // kSegPathMaxRows rows the segment kernels (ceil(V / 4096) workgroups per row) finish sooner.
+  // Both give the same integers.
+  if (vec && V <= kRowMaxV && rows > kSegPathMaxRows) {
     hipLaunchKernelGGL(cdf24_row_kernel, dim3(rows), dim3(kRowThreads), 0, s, p, V, total, cdf,
                        status);
     NC_HIP(hipGetLastError());

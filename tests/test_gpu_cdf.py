@@ -39,6 +39,22 @@ def test_random_full_vocab_rows(nc):
     _check(nc, rows.astype(np.float32))
 
 
+@pytest.mark.parametrize("n", [16, 64, 65, 80])
+def test_full_vocab_both_launch_paths(nc, n):
+    """At V = 49,152 up to 64 rows run the segment kernels and more rows the one-workgroup-per-row
+    kernel; both must equal the oracle, and a row's CDF must not depend on the batch it is in."""
+    rng = np.random.default_rng(100 + n)
+    alphas = (0.005, 0.05, 0.5, 5.0)
+    rows = np.stack([rng.dirichlet(np.full(49152, alphas[i % 4])) for i in range(n)])
+    rows = rows.astype(np.float32)
+    rows[n // 2] = 0.0
+    rows[n // 2, 12345] = 1.0
+    _check(nc, rows)
+    head, _ = _gpu_cdf(nc, rows[:16])
+    full, _ = _gpu_cdf(nc, rows)
+    assert np.array_equal(head, full[:16])
+
+
 def test_worked_examples(nc):
     rows = np.full((1, 512), 2.0 ** -9, dtype=np.float32)
     cdf, st = _gpu_cdf(nc, rows)
