@@ -119,7 +119,7 @@ void nc_destroy(nc_ctx* ctx);
 
 /* Reset (and size) the per-stream state for n_streams streams of up to max_tokens tokens each:
  * KV caches, n-gram tables, bias vectors, mixer weights and histories are cleared
- * (Algorithm 1 "Initialize").  NC_E_INVALID if n_streams > cfg.max_streams. */
+ * (Algorithm 1, initialisation).  NC_E_INVALID if n_streams > cfg.max_streams. */
 nc_status nc_streams_reset(nc_ctx* ctx, uint32_t n_streams, uint32_t max_tokens);
 
 /* Static FP8 activation scales (per-tensor amax / 448), calibrated by running the FP32 model
@@ -136,9 +136,11 @@ nc_status nc_calibrate_fp8(nc_ctx* ctx, const int32_t* tokens, size_t n);
 nc_status nc_probs_for_context(nc_ctx* ctx, uint32_t stream, const int32_t* tokens, size_t n,
                                float* probs, nc_probe* probe);
 
-/* Algorithm 1 "Update: N-gram, Mixer, AdaptiveHead with t_i": commit `token` as the next token
- * of `stream`, using the distribution of the last nc_probs_for_context() at that position
- * (computed on demand if there was none). */
+/* Algorithm 1, the update step after a token is coded: commit `token` as the next token of
+ * `stream`.  The n-gram counts always take the token; the bias head and the mixer weights take
+ * their SGD and exponential-weights steps when the position's mode ran the LLM (respectively
+ * mixed), exactly as in nc_encode_stream.  The position's distribution is recomputed from the
+ * committed state, so the result does not depend on whether nc_probs_for_context was called. */
 nc_status nc_mix_update(nc_ctx* ctx, uint32_t stream, int32_t token);
 
 /* CDF-24 quantisation, section 3.4 (Algorithm 1 probs_to_cdf(p, 2^24)): for each of `rows`
@@ -148,7 +150,12 @@ nc_status nc_mix_update(nc_ctx* ctx, uint32_t stream, int32_t token);
  * row_status: device, rows int32 (0 ok, 1 = NaN/negative/>1 probability or mass above total,
  * in which case that row's cdf is unspecified); may be NULL.  Pure: no context needed.
  * Errors: NC_E_INVALID for vocab outside [1, 262144], total <= vocab, total > 2^24, NULL
- * pointers.  Uses a library-owned device workspace (rows * ceil(vocab/4096) * 16 bytes). */
+ * pointers.  Uses a library-owned device workspace of rows * ceil(vocab/4096) * 16 bytes, one per
+ * (device, stream): calls on one stream share it in stream order, calls on different streams
+ * (also from different host threads) never share it.  The first call on a stream, and a call that
+ * needs more than that stream's buffer holds, allocates (hipMalloc; a grown buffer is freed after
+ * its stream has drained, which blocks the host), so such a call cannot be captured into a
+ * HIP graph. */
 nc_status nc_quantize_cdf24(const float* probs, uint32_t rows, uint32_t vocab, uint32_t total,
                             uint32_t* cdf, int32_t* row_status, void* stream);
 
@@ -279,7 +286,8 @@ nc_status nc_ac_decode_static(const uint8_t* in, size_t in_bytes, const uint32_t
  * p = w_0 q0 + sum_{j>=1} w_j P_j, loss[r] = -log p(t*_r).  All device pointers:
  * z rows x vocab, b vocab, theta n_experts, P rows x (n_experts-1) x vocab, target rows int32;
  * outputs loss rows, p rows x vocab (may be NULL), resp rows x n_experts (responsibilities
- * r_j = w_j q_j(t*) / p(t*), needed by the backward).  n_experts <= 8. */
+ * r_j = w_j q_j(t*) / p(t*), needed by the backward).  n_experts <= 8.  Workspace: as for
+ * nc_quantize_cdf24 (one library-owned buffer per device and stream, grown on demand). */
 nc_status nc_ensemble_forward(const float* z, const float* b, const float* theta,
                               const float* P, const int32_t* target, uint32_t rows,
                               uint32_t vocab, uint32_t n_experts, float* loss, float* p,
@@ -288,7 +296,8 @@ nc_status nc_ensemble_forward(const float* z, const float* b, const float* theta
 /* Backward: grad_b[t] = sum_r g_r r_{r,0} (q0_r(t) - 1[t = t*_r]),
  * grad_theta[j] = sum_r g_r (w_j - r_{r,j}), with g = grad_loss (device, rows) -- a fixed-order
  * reduction over rows (no float atomics).  If lr != 0 the SGD step b -= lr grad_b,
- * theta -= lr grad_theta is applied in place as well (b, theta writable device pointers). */
+ * theta -= lr grad_theta is applied in place as well (b, theta writable device pointers).
+ * Workspace: as for nc_ensemble_forward. */
 nc_status nc_ensemble_backward(const float* z, float* b, float* theta, const float* resp,
                                const int32_t* target, const float* grad_loss, uint32_t rows,
                                uint32_t vocab, uint32_t n_experts, float lr, float* grad_b,

@@ -3,7 +3,8 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <unordered_map>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "coder.hpp"
@@ -15,23 +16,29 @@ namespace nc {
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
-// Device workspace of the context-free calls, one growing buffer per device.  hipFree of a
-// smaller old buffer synchronises the device, so work still using it has finished.
-static void* pure_call_workspace(size_t bytes) {
+// Device workspace of the context-free calls: one buffer per (device, stream).  Work queued on one
+// stream runs in order, so calls on the same stream can share a buffer; calls on different streams
+// never do.  The lock is held until the launch is queued, and a buffer that must grow is freed
+// only after its stream has drained, so no queued kernel can lose its workspace.
+template <class Launch>
+static void with_workspace(hipStream_t stream, size_t bytes, Launch&& launch) {
   static std::mutex mu;
-  static std::unordered_map<int, std::pair<void*, size_t>> bufs;
+  static std::map<std::pair<int, hipStream_t>, std::pair<void*, size_t>> bufs;
   int dev = 0;
   NC_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(mu);
-  auto& b = bufs[dev];
+  auto& b = bufs[{dev, stream}];
   if (b.second < bytes) {
-    if (b.first) NC_HIP(hipFree(b.first));
+    if (b.first) {
+      NC_HIP(hipStreamSynchronize(stream));
+      NC_HIP(hipFree(b.first));
+    }
     b.first = nullptr;
     b.second = 0;
     NC_HIP(hipMalloc(&b.first, bytes));
     b.second = bytes;
   }
-  return b.first;
+  launch(b.first);
 }
 }  // namespace nc
 
@@ -51,9 +58,10 @@ nc_status nc_quantize_cdf24(const float* probs, uint32_t rows, uint32_t vocab, u
     NC_CHECK(total > vocab && total <= (1u << 24), NC_E_INVALID,
              "total must satisfy vocab < total <= 2^24");
     if (rows == 0) return;
-    void* ws = pure_call_workspace(quantize_workspace_bytes(rows, vocab));
-    launch_quantize_cdf(probs, rows, vocab, total, cdf, row_status, ws,
-                        static_cast<hipStream_t>(stream));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    with_workspace(st, quantize_workspace_bytes(rows, vocab), [&](void* ws) {
+      launch_quantize_cdf(probs, rows, vocab, total, cdf, row_status, ws, st);
+    });
   });
 }
 
@@ -122,9 +130,11 @@ nc_status nc_ensemble_forward(const float* z, const float* b, const float* theta
     NC_CHECK(n_experts >= 1 && n_experts <= kMaxExperts, NC_E_INVALID, "n_experts in [1, 8]");
     NC_CHECK(vocab >= 1 && vocab <= 262144u, NC_E_INVALID, "vocab must be in [1, 262144]");
     if (rows == 0) return;
-    void* ws = pure_call_workspace(ensemble_workspace_bytes(int(rows), int(vocab)));
-    launch_ensemble_forward(z, b, theta, P, target, int(rows), int(vocab), int(n_experts), loss,
-                            p, resp, ws, static_cast<hipStream_t>(stream));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    with_workspace(st, ensemble_workspace_bytes(int(rows), int(vocab)), [&](void* ws) {
+      launch_ensemble_forward(z, b, theta, P, target, int(rows), int(vocab), int(n_experts), loss,
+                              p, resp, ws, st);
+    });
   });
 }
 
@@ -137,10 +147,11 @@ nc_status nc_ensemble_backward(const float* z, float* b, float* theta, const flo
     NC_CHECK(n_experts >= 1 && n_experts <= kMaxExperts, NC_E_INVALID, "n_experts in [1, 8]");
     NC_CHECK(vocab >= 1 && vocab <= 262144u, NC_E_INVALID, "vocab must be in [1, 262144]");
     if (rows == 0) return;
-    void* ws = pure_call_workspace(ensemble_workspace_bytes(int(rows), int(vocab)));
-    launch_ensemble_backward(z, b, theta, resp, target, grad_loss, int(rows), int(vocab),
-                             int(n_experts), lr, grad_b, grad_theta, ws,
-                             static_cast<hipStream_t>(stream));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    with_workspace(st, ensemble_workspace_bytes(int(rows), int(vocab)), [&](void* ws) {
+      launch_ensemble_backward(z, b, theta, resp, target, grad_loss, int(rows), int(vocab),
+                               int(n_experts), lr, grad_b, grad_theta, ws, st);
+    });
   });
 }
 

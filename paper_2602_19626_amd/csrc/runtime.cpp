@@ -940,6 +940,7 @@ void check_config(const nc_config* cfg) {
   NC_CHECK(cfg->max_streams >= 1, NC_E_INVALID, "max_streams must be >= 1");
   NC_CHECK(cfg->mix_w_llm > 0.f && cfg->mix_w_llm < 1.f, NC_E_INVALID, "mix_w_llm in (0, 1)");
   NC_CHECK(cfg->ngram_eps > 0.f, NC_E_INVALID, "ngram_eps must be positive");
+  NC_CHECK(cfg->ngram_max_contexts >= 1, NC_E_INVALID, "ngram_max_contexts must be >= 1");
 }
 
 void validate_tokens(const nc_ctx* c, const int32_t* t, size_t n) {

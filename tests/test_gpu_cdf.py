@@ -129,3 +129,27 @@ def test_batch_and_interval_lookup(nc):
         assert tuple(enc[r]) == (tok[r], ref[tok[r]], ref[tok[r] + 1])
         s = int(np.searchsorted(ref, targets[r], side="right") - 1)
         assert tuple(dec[r].astype(np.int64)) == (s, ref[s], ref[s + 1])
+
+
+def test_two_streams_do_not_share_a_workspace(nc):
+    """Two row sets (both on the segment path, which keeps partials in the workspace) quantised on
+    two streams whose work overlaps: each equals the oracle."""
+    rng = np.random.default_rng(7)
+    a = np.stack([rng.dirichlet(np.full(49152, 0.05)) for _ in range(48)]).astype(np.float32)
+    b = np.stack([rng.dirichlet(np.full(49152, 2.0)) for _ in range(40)]).astype(np.float32)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for _ in range(3):
+        outs.append((nc.quantize_cdf24(ta, stream=s1), nc.quantize_cdf24(tb, stream=s2)))
+    torch.cuda.synchronize()
+    for (ca, sa), (cb, sb) in outs:
+        ca = ca.cpu().numpy().view(np.uint32)
+        cb = cb.cpu().numpy().view(np.uint32)
+        assert not sa.cpu().numpy().any() and not sb.cpu().numpy().any()
+        for r in range(0, 48, 5):
+            assert np.array_equal(ca[r].astype(np.int64), quantize_cdf(a[r])), r
+        for r in range(0, 40, 5):
+            assert np.array_equal(cb[r].astype(np.int64), quantize_cdf(b[r])), r

@@ -70,3 +70,15 @@ def test_error_paths():
     with pytest.raises(nc.NacrithError) as e:
         nc.ac_decode_static(b"\xff" * 2, cdf, 100)           # 100 bits from 16: corrupt
     assert e.value.status == 5
+
+
+def test_create_rejects_invalid_configs_before_touching_the_device():
+    """nc_create validates the configuration first, so these fail with NC_E_INVALID on any host."""
+    import synth
+    w = np.zeros(16, np.float32)
+    for over in (dict(ngram_max_contexts=0), dict(ngram_order=5), dict(max_streams=0),
+                 dict(ngram_eps=0.0), dict(cdf_total=512)):
+        cfg = nc.make_config(synth.TINY, **{**dict(ngram_order=3), **over})
+        with pytest.raises(nc.NacrithError) as e:
+            nc.Context(cfg, w)
+        assert e.value.status == 1, over
