@@ -30,6 +30,14 @@ cache: a kept entry keeps the value it got when its token was appended).
 Tokens appended together are evaluated with a causal mask, which is the per-token definition
 above written for several tokens at once; a block never spans a slide.
 
+Error model of the reduced-precision forms (test infrastructure only; off by default): an optional
+``operand_noise(array, kind)`` callable is applied to every matrix-product operand -- kind
+"weight" once to each projection matrix and to the output copy of E (the embedding lookup keeps
+the exact E), kind "act" to the inputs of the projections and of the output layer, kind "att" to
+the attention operands q, k, v and the softmax weights.  The reduced-precision tolerances are
+derived from runs with a rounding-sized perturbation there; without the callable the arithmetic
+above is unchanged.
+
 Pinned by: torch float64 library attention/norm composition on a tiny model, the relative-shift
 invariance of RoPE, single-key attention, GQA with one query head per kv head, the zero-layer
 model (tests/test_oracle_transformer.py).
@@ -48,9 +56,16 @@ def silu(x: np.ndarray) -> np.ndarray:
 
 
 class Transformer:
-    def __init__(self, shape, weights: dict, max_block: int = 512):
+    def __init__(self, shape, weights: dict, max_block: int = 512, operand_noise=None):
         self.shape = shape
         self.w = {k: np.asarray(v, dtype=np.float64) for k, v in weights.items()}
+        self.noise = operand_noise
+        self.w_out = self.w["E"]
+        if operand_noise is not None:
+            for k in self.w:
+                if k.split(".")[-1] in ("Wq", "Wk", "Wv", "Wo", "Wg", "Wu", "Wd"):
+                    self.w[k] = operand_noise(self.w[k], "weight")
+            self.w_out = operand_noise(self.w["E"], "weight")
         hd = shape.head_dim
         self.inv_freq = shape.rope_theta ** (-(2.0 * np.arange(hd // 2, dtype=np.float64)) / hd)
         self.max_block = max_block
@@ -81,8 +96,11 @@ class Transformer:
         self.n_slides += 1
         self.cache_len -= c
 
+    def _op(self, a: np.ndarray, kind: str) -> np.ndarray:
+        return a if self.noise is None else self.noise(a, kind)
+
     def _block(self, tokens: np.ndarray) -> np.ndarray:
-        s, w = self.shape, self.w
+        s, w, op = self.shape, self.w, self._op
         n = len(tokens)
         base = self.cache_len
         pos = base + np.arange(n, dtype=np.float64)
@@ -91,11 +109,11 @@ class Transformer:
         x = w["E"][tokens]
         for l in range(s.n_layers):
             p = f"l{l}."
-            y = rmsnorm(x, w[p + "attn_norm"], s.norm_eps)
+            y = op(rmsnorm(x, w[p + "attn_norm"], s.norm_eps), "act")
             q = (y @ w[p + "Wq"].T).reshape(n, hq, hd)
             k = (y @ w[p + "Wk"].T).reshape(n, hk, hd)
-            v = (y @ w[p + "Wv"].T).reshape(n, hk, hd)
-            q, k = self.rope(q, pos), self.rope(k, pos)
+            v = op((y @ w[p + "Wv"].T).reshape(n, hk, hd), "att")
+            q, k = op(self.rope(q, pos), "att"), op(self.rope(k, pos), "att")
             self.K[l] = np.concatenate([self.K[l], k], axis=0)
             self.V[l] = np.concatenate([self.V[l], v], axis=0)
             kk, vv = self.K[l], self.V[l]                       # [base + n, hk, hd]
@@ -109,10 +127,10 @@ class Transformer:
                 sc -= sc.max(axis=1, keepdims=True)
                 a = np.exp(sc)
                 a /= a.sum(axis=1, keepdims=True)
-                o[:, h, :] = a @ vv[:, g, :]
-            x = x + o.reshape(n, hq * hd) @ w[p + "Wo"].T
-            y = rmsnorm(x, w[p + "mlp_norm"], s.norm_eps)
-            x = x + (silu(y @ w[p + "Wg"].T) * (y @ w[p + "Wu"].T)) @ w[p + "Wd"].T
+                o[:, h, :] = op(a, "att") @ vv[:, g, :]
+            x = x + op(o.reshape(n, hq * hd), "act") @ w[p + "Wo"].T
+            y = op(rmsnorm(x, w[p + "mlp_norm"], s.norm_eps), "act")
+            x = x + op(silu(y @ w[p + "Wg"].T) * (y @ w[p + "Wu"].T), "act") @ w[p + "Wd"].T
         self.n_appended += n
         self.cache_len += n
         return rmsnorm(x, w["final_norm"], s.norm_eps)
@@ -131,4 +149,4 @@ class Transformer:
         return np.concatenate(out, axis=0) if out else np.zeros((0, self.shape.d_model))
 
     def logits(self, hidden: np.ndarray) -> np.ndarray:
-        return hidden @ self.w["E"].T
+        return self._op(hidden, "act") @ self.w_out.T

@@ -61,7 +61,7 @@ def test_autograd_backward_matches_oracle_and_finite_differences(dev, seed):
     # closed-form oracle gradient on the float32-rounded inputs
     z32, b32, th32, P32 = (np.float64(np.float32(x)) for x in (z, b, theta, P))
     ref_loss, ref_gb, ref_gth = _oracle_grads(z32, b32, th32, P32, t)
-    assert abs(float(loss.sum()) - ref_loss) / abs(ref_loss) < 1e-5
+    assert abs(float(loss.detach().sum()) - ref_loss) / abs(ref_loss) < 1e-5
     assert np.linalg.norm(gb - ref_gb) / np.linalg.norm(ref_gb) < 1e-4
     assert np.linalg.norm(gth - ref_gth) / np.linalg.norm(ref_gth) < 1e-4
     # central finite differences of the FP64 oracle loss (h = 1e-4)
@@ -112,3 +112,49 @@ def test_ensemble_pipeline_matches_oracle_and_roundtrips(dev):
     data, bits = ctx.encode_stream([toks])
     assert np.array_equal(ctx.decode_stream(data, [len(toks)])[0], toks)
     assert (bits[0] - orc.ideal_bits) / len(toks) < 0.01
+
+
+def test_backward_at_full_vocabulary_64_rows(dev):
+    """The differentiation workload's own size: V = 49,152 and 64 rows (one per stream of the
+    batch), five experts.  GPU gradients against the oracle's closed form, norm-wise 1e-4 and per
+    element (relative 1e-4 with an absolute floor of 1e-10), and against central finite
+    differences of the oracle loss (h = 1e-4, FP64), summed row by row so that the cancellation
+    of each difference stays at the rounding of one row's loss."""
+    from paper_2602_19626_amd.ensemble import ensemble_loss
+    z, b, theta, P, t = _case(11, rows=64, v=49152)
+    tz = torch.tensor(z, dtype=torch.float32, device=dev)
+    tb = torch.tensor(b, dtype=torch.float32, device=dev, requires_grad=True)
+    tth = torch.tensor(theta, dtype=torch.float32, device=dev, requires_grad=True)
+    tP = torch.tensor(P, dtype=torch.float32, device=dev).contiguous()
+    tt = torch.tensor(t, dtype=torch.int32, device=dev)
+    loss = ensemble_loss(tz, tb, tth, tP, tt)
+    loss.sum().backward()
+    gb = tb.grad.double().cpu().numpy()
+    gth = tth.grad.double().cpu().numpy()
+    z32, b32, th32, P32 = (np.float64(np.float32(x)) for x in (z, b, theta, P))
+    ref_loss, ref_gb, ref_gth = _oracle_grads(z32, b32, th32, P32, t)
+    assert abs(float(loss.detach().sum()) - ref_loss) / abs(ref_loss) < 1e-5
+    assert np.linalg.norm(gb - ref_gb) / np.linalg.norm(ref_gb) < 1e-4
+    assert np.linalg.norm(gth - ref_gth) / np.linalg.norm(ref_gth) < 1e-4
+    assert np.all(np.abs(gb - ref_gb) <= 1e-4 * np.abs(ref_gb) + 1e-10)
+    assert np.all(np.abs(gth - ref_gth) <= 1e-4 * np.abs(ref_gth) + 1e-10)
+
+    h = 1e-4
+    rows = range(z.shape[0])
+
+    def fd(th_p, b_p, th_m, b_m):
+        return sum((EnsembleGate.loss(th_p, b_p, z32[r], list(P32[r]), int(t[r]))
+                    - EnsembleGate.loss(th_m, b_m, z32[r], list(P32[r]), int(t[r]))) / (2 * h)
+                   for r in rows)
+
+    fd_th = np.array([fd(th32 + h * e, b32, th32 - h * e, b32) for e in np.eye(len(theta))])
+    assert np.linalg.norm(gth - fd_th) / np.linalg.norm(fd_th) < 1e-4
+    idx = np.unique(np.concatenate([t[:12], np.arange(0, z.shape[1], 4099)]))
+    fd_b = []
+    for i in idx:
+        e = np.zeros_like(b32)
+        e[i] = h
+        fd_b.append(fd(th32, b32 + e, th32, b32 - e))
+    fd_b = np.array(fd_b)
+    assert np.linalg.norm(gb[idx] - fd_b) / np.linalg.norm(fd_b) < 1e-4
+    assert np.all(np.abs(gb[idx] - fd_b) <= 1e-4 * np.abs(fd_b) + 1e-9)

@@ -1,6 +1,20 @@
-"""GPU parity at the 135M shape (30 layers, d 576, 9/3 heads, V 49,152) against the FP64 oracle:
-FP32 logits within 1e-3 across the first KV slide, BF16 and FP8 within their stated tolerances,
-CDF-24 bit-exact on the GPU's probabilities, exact round trips, batch invariance."""
+"""GPU parity at the 135M shape (30 layers, d 576, 9/3 heads, V 49,152) against the FP64 oracle.
+
+Two oracle runs over the same 2,200-token stream (the cache of L = 2,048 slides by C = 512 when
+x_2048 is appended, so positions from 2048 on are computed against the post-slide cache, section
+3.10):
+
+* skip off: the LLM runs at every position, so logits are compared across the slide for FP32
+  (within 1e-3), BF16 and FP8 (tolerances from an error model of each format run on the oracle),
+  and p~, p_ng and p element by element at V = 49,152;
+* the method as specified (entropy skip, section 3.8): modes, the skipped positions' p = p_ng,
+  CDF-24 of the GPU's own probabilities, and a 2,200-token round trip whose coded bit count equals
+  the oracle coder's on its own FP64 distributions.
+"""
+import dataclasses
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -12,79 +26,155 @@ from tests.nc_util import gpu_available, kl_bits, make_context
 pytestmark = pytest.mark.gpu
 
 WL = synth.WORKLOADS["full_fp32"]
+WL_NOSKIP = dataclasses.replace(WL, skip="none")
 N = 2200                                   # crosses the first slide at position 2048
-POS = [0, 1, 2, 99, 100, 101, 1000, 2047, 2048, 2049, 2199]
-# Stated tolerances of the reduced-precision GEMM paths (max |logit error| vs the FP64 oracle
-# over the sampled positions, and the mean KL of the LLM softmax in bits).
-TOL = {"fp32": (1e-3, 1e-6), "bf16": (0.05, 2e-3), "fp8": (0.25, 2e-2)}
+POS = [0, 1, 2, 99, 100, 101, 500, 1000, 1500, 2046, 2047, 2048, 2049, 2100, 2199]
+# Tolerances of the GEMM precision forms against the FP64 oracle: max |logit error| over the
+# sampled positions, and the mean KL(p_llm,oracle || p_llm,gpu) in bits.  FP32: 1e-3 (the stated
+# target; float32 sums of 576-1,536 terms err by ~1e-6).  BF16 and FP8: the error model of
+# tests/golden/make_precision_tolerances.py (the FP64 oracle with every matrix-product operand
+# perturbed by the format's unit roundoff, the largest result over its seeds).
+_PT = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                  "precision_tolerances.json")))
+TOL = {"fp32": (1e-3, 1e-6)}
+TOL.update({f: (_PT[f]["max_abs_logit"], _PT[f]["mean_kl_bits"]) for f in ("bf16", "fp8")})
+# Element-wise bounds at FP32 (relative to the oracle's value):
+#   p_ng: integer counts, then ~3 float32 operations per order: <= 1e-5;
+#   p~ = exp(z_t + b_t - lse): log p~ moves by dz_t - dlse with |dlse| <= max|dz|, plus ~30
+#     roundings of the segment sums: <= 2 max|dz| + 1e-5 at that position;
+#   p = w_0 p~ + w_1 p_ng: the larger of the two plus the mixer weights' relative error, which
+#     sums the per-step errors of log p_j(t*) over the mixing steps: stated bound 1e-3.
+REL_PNG, REL_P = 1e-5, 1e-3
+
+
+def _stream():
+    return synth.workload_streams(WL, max_len=N)[0]
 
 
 @pytest.fixture(scope="module")
-def oracle_run():
+def weights():
     if not gpu_available():
         pytest.skip("no GPU")
-    w = synth.make_weights(WL.shape, WL.weight_seed)
-    toks = synth.workload_streams(WL, max_len=N)[0]
-    orc = op.encode(op.Settings.from_workload(WL), WL.shape, w, toks, record=POS,
-                    quantize=False, block=512)
-    return w, toks, orc
+    return synth.make_weights(WL.shape, WL.weight_seed)
+
+
+@pytest.fixture(scope="module")
+def oracle_noskip(weights):
+    s = op.Settings.from_workload(WL_NOSKIP)
+    assert not s.use_skip
+    return op.encode(s, WL.shape, weights, _stream(), record=POS, quantize=False, block=512)
+
+
+@pytest.fixture(scope="module")
+def oracle_skip(weights):
+    return op.encode(op.Settings.from_workload(WL), WL.shape, weights, _stream(), record=POS,
+                     quantize=True, block=512)
+
+
+def _fp8_calibrate(ctx):
+    ctx.calibrate_fp8(synth.make_stream(2048, WL.shape.vocab, seed=synth.CALIBRATION_SEED,
+                                        span=WL.span))
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a, np.float64) - b) / np.asarray(b, np.float64)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_logits_and_coding_distributions(oracle_run, prec):
-    w, toks, orc = oracle_run
-    ctx, _ = make_context(WL, precision=prec, max_streams=1)
+def test_logits_across_the_slide(oracle_noskip, prec):
+    """Skip off on both sides: every sampled position runs the LLM, including 2047 (full cache),
+    2048 (the slide) and 2049 / 2100 / 2199 (stale K/V of the kept 1,536 entries)."""
+    toks = _stream()
+    ctx, _ = make_context(WL_NOSKIP, precision=prec, max_streams=1)
     if prec == "fp8":
-        calib = synth.make_stream(2048, WL.shape.vocab, seed=synth.CALIBRATION_SEED, span=WL.span)
-        ctx.calibrate_fp8(calib)
+        _fp8_calibrate(ctx)
     ctx.reset(1, N + 1)
-    zerr, kls = [], []
+    zerr, kls, rows = [], [], []
     for i in POS:
         p, pr = ctx.probs_for_context(0, toks[:i], probe=True)
-        rec = orc.records[i]
-        if rec["mode"] != op.MODE_SKIP and pr["llm_ran"]:
-            zerr.append(float(np.max(np.abs(pr["logits"] - rec["z"]))))
-            z = pr["logits"].astype(np.float64)
-            q = np.exp(z - z.max())
-            kls.append(kl_bits(rec["p_llm"], q / q.sum()))
-        # CDF-24 of the GPU's own coding distribution is bit-exact with the oracle quantiser
-        assert np.array_equal(pr["cdf"].astype(np.int64), quantize_cdf(p.astype(np.float32)))
+        rec = oracle_noskip.records[i]
+        assert pr["llm_ran"] and rec["mode"] != op.MODE_SKIP, i
+        dz = float(np.max(np.abs(pr["logits"] - rec["z"])))
+        zerr.append(dz)
+        z = pr["logits"].astype(np.float64)
+        q = np.exp(z - z.max())
+        kls.append(kl_bits(rec["p_llm"], q / q.sum()))
+        # p~ from the logits and the bias head: log p~ moves by at most 2 max|dz| (+ rounding)
+        assert np.max(_rel(pr["ptilde"], rec["ptilde"])) <= np.expm1(2 * dz) + 1e-5, i
+        # the n-gram does not depend on the LLM or the precision
+        assert np.max(_rel(pr["p_ngram"], rec["p_ng"])) <= REL_PNG, i
+        assert abs(pr["entropy_bits"] - rec["entropy"]) < 1e-3, i
+        assert pr["mode"] == rec["mode"], i
         if prec == "fp32":
-            assert pr["mode"] == rec["mode"] or abs(pr["entropy_bits"] - 1.5) < 1e-4, i
-            if pr["mode"] == rec["mode"]:
-                assert kl_bits(rec["p"], p) < 1e-5, i
+            assert np.max(_rel(p, rec["p"])) <= REL_P, i
+            if rec["mode"] == op.MODE_MIX:
+                assert np.allclose(pr["mix_w"], rec["mix_w"], rtol=REL_P, atol=1e-30), i
+        assert np.array_equal(pr["cdf"].astype(np.int64), quantize_cdf(p.astype(np.float32))), i
+        rows.append((i, dz))
     tz, tk = TOL[prec]
-    print(f"{prec}: max|dz| {max(zerr):.3e}  mean KL(llm) {np.mean(kls):.3e} bits")
+    print(f"{prec}: max|dz| {max(zerr):.3e} (per position {rows})  "
+          f"mean KL(llm) {np.mean(kls):.3e} bits")
+    assert any(i >= 2048 for i in POS) and POS == _PT["positions"]
     assert max(zerr) < tz
     assert np.mean(kls) < tk
 
 
+def test_modes_and_skipped_distributions(oracle_skip):
+    """The method as specified (entropy skip): modes agree (a disagreement is accepted only within
+    1e-4 bits of the 1.5-bit threshold), p agrees element by element, the CDF is bit-exact on the
+    GPU's probabilities."""
+    toks = _stream()
+    ctx, _ = make_context(WL, precision="fp32", max_streams=1)
+    ctx.reset(1, N + 1)
+    n_skip = 0
+    for i in POS:
+        p, pr = ctx.probs_for_context(0, toks[:i], probe=True)
+        rec = oracle_skip.records[i]
+        if pr["mode"] != rec["mode"]:
+            assert abs(rec["entropy"] - 1.5) < 1e-4, i
+            continue
+        n_skip += rec["mode"] == op.MODE_SKIP
+        assert np.max(_rel(pr["p_ngram"], rec["p_ng"])) <= REL_PNG, i
+        assert np.max(_rel(p, rec["p"])) <= REL_P, i
+        assert np.array_equal(pr["cdf"].astype(np.int64), quantize_cdf(p.astype(np.float32))), i
+    assert n_skip >= 5                        # the sample reaches the skip branch
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_roundtrip_full_shape(oracle_run, prec):
-    w, toks, orc = oracle_run
+def test_roundtrip_across_the_slide(oracle_skip, prec):
+    """A 2,200-token stream (one slide) round-trips exactly in every precision form; in FP32 the
+    coded bit count equals the oracle coder's on its own FP64 distributions, in BF16 and FP8 it is
+    within 0.01 bits/token of it."""
+    toks = _stream()
     ctx, _ = make_context(WL, precision=prec, max_streams=3)
     if prec == "fp8":
-        ctx.calibrate_fp8(synth.make_stream(2048, WL.shape.vocab, seed=synth.CALIBRATION_SEED,
-                                            span=WL.span))
-    t = toks[:700]
-    data, bits = ctx.encode_stream([t])
-    out = ctx.decode_stream(data, [len(t)])
-    assert np.array_equal(out[0], t)
-    streams = [t, synth.make_stream(300, WL.shape.vocab, seed=77, span=WL.span),
+        _fp8_calibrate(ctx)
+    data, bits = ctx.encode_stream([toks])
+    out = ctx.decode_stream(data, [len(toks)])
+    assert np.array_equal(out[0], toks)
+    print(f"{prec}: GPU {bits[0]} bits, oracle coder {oracle_skip.n_bits} bits, oracle ideal "
+          f"{oracle_skip.ideal_bits:.1f}")
+    if prec == "fp32":
+        assert bits[0] == oracle_skip.n_bits
+        assert len(data[0]) == len(oracle_skip.data)
+    else:
+        # the precision forms change only the LLM's share of the mix: within 0.01 bits/token of
+        # the oracle coder's length
+        assert abs(bits[0] - oracle_skip.n_bits) / len(toks) < 0.01
+    streams = [toks[:700], synth.make_stream(300, WL.shape.vocab, seed=77, span=WL.span),
                synth.make_stream(520, WL.shape.vocab, seed=78, span=WL.span)]
     together, _ = ctx.encode_stream(streams)
-    assert together[0] == data[0]
+    assert together[0] == ctx.encode_stream([streams[0]])[0][0]
     assert together[1] == ctx.encode_stream([streams[1]])[0][0]
     dec = ctx.decode_stream(together, [len(s) for s in streams])
     for a, b in zip(dec, streams):
         assert np.array_equal(a, b)
 
 
-def test_many_streams_batch_and_alone_agree_bf16(oracle_run):
+def test_many_streams_batch_and_alone_agree_bf16(weights):
     """24 BF16 streams coded together (prefill passes of thousands of attention items, one wave
     per item) and alone (a few hundred items per pass, a workgroup per quad plus the fold kernel)
     give the same bytes, and the batch decodes back exactly."""
-    w, toks, orc = oracle_run
     ctx, _ = make_context(WL, precision="bf16", max_streams=24)
     streams = [synth.make_stream(150 + 7 * s, WL.shape.vocab, seed=300 + s, span=WL.span)
                for s in range(24)]

@@ -134,3 +134,49 @@ def test_zero_layer_model_is_normed_embedding_product():
     for i, t in enumerate([3, 9, 400]):
         ref = (e[t] / np.sqrt(np.mean(e[t] ** 2) + shape.norm_eps)) @ e.T
         assert np.max(np.abs(z[i] - ref)) < 1e-13
+
+
+def test_operand_noise_hook_is_off_by_default_and_reaches_every_product():
+    """The error-model hook: an identity callable leaves every logit bit-identical; a callable that
+    scales one kind of operand by (1 + u) moves the logits, and scaling the output copy of E alone
+    scales the logits by exactly (1 + u) (the embedding lookup keeps the exact E)."""
+    w = synth.make_weights(synth.TINY, 0)
+    toks = [0, 5, 9, 3, 3, 7, 100, 2]
+    ref = Transformer(synth.TINY, w)
+    z0 = ref.logits(ref.append(toks))
+    seen = set()
+
+    def ident(a, kind):
+        seen.add(kind)
+        return a
+    m = Transformer(synth.TINY, w, operand_noise=ident)
+    assert np.array_equal(m.logits(m.append(toks)), z0)
+    assert seen == {"weight", "act", "att"}
+    for kind in ("act", "att"):
+        m = Transformer(synth.TINY, w, operand_noise=lambda a, k: a * 1.01 if k == kind else a)
+        assert np.max(np.abs(m.logits(m.append(toks)) - z0)) > 1e-6, kind
+    e_only = {"n": 0}
+
+    def head_only(a, kind):
+        if kind == "weight" and a.shape == w["E"].shape:
+            e_only["n"] += 1
+            return a * 2.0
+        return a
+    m = Transformer(synth.TINY, w, operand_noise=head_only)
+    assert e_only["n"] == 1
+    assert np.array_equal(m.logits(m.append(toks)), 2.0 * z0)
+
+
+def test_precision_tolerances_file_matches_the_parity_test():
+    """The stored error-model tolerances cover the parity test's positions, and each format's
+    stored value is the largest over its seeds."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "precision_tolerances.json")
+    d = json.load(open(path))
+    assert max(d["positions"]) >= 2048
+    for f, u in (("bf16", 2.0 ** -8), ("fp8", 2.0 ** -4)):
+        assert d[f]["u_weights_activations"] == u and d[f]["u_attention"] == 2.0 ** -8
+        assert d[f]["max_abs_logit"] == max(r["max_abs_logit"] for r in d[f]["runs"])
+        assert d[f]["mean_kl_bits"] == max(r["mean_kl_bits"] for r in d[f]["runs"])
+    assert d["bf16"]["max_abs_logit"] < d["fp8"]["max_abs_logit"]
