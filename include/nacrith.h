@@ -159,6 +159,21 @@ nc_status nc_mix_update(nc_ctx* ctx, uint32_t stream, int32_t token);
 nc_status nc_quantize_cdf24(const float* probs, uint32_t rows, uint32_t vocab, uint32_t total,
                             uint32_t* cdf, int32_t* row_status, void* stream);
 
+/* nc_quantize_cdf24 for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): same arguments, same integers, but
+ * its kernels take their workspace from a fixed device array of 65,536 segment partials
+ * (1 MiB per GPU, held until the process ends) instead of a library-allocated buffer; it calls
+ * no hipMalloc or hipFree.  The workspace is needed on the segment path (up to 64 rows, rows not
+ * 16-byte aligned or with vocab not a multiple of 4, or vocab > 49,152): there rows *
+ * ceil(vocab / 4096) must not exceed 65,536, else NC_E_CAPACITY and nothing is launched.  Every
+ * call on one GPU shares that GPU's array (nothing in it needs clearing between calls), so two
+ * calls whose work overlaps on one GPU -- on different streams, or from different threads --
+ * race and give unspecified CDFs; serialise them on one stream.  The first call on a device
+ * resolves the array's address there (hipGetSymbolAddress). */
+nc_status nc_quantize_cdf24_noalloc(const float* probs, uint32_t rows, uint32_t vocab,
+                                    uint32_t total, uint32_t* cdf, int32_t* row_status,
+                                    void* stream);
+
 /* Interval lookup on CDF rows (section 3.9): mode 0 (encode) key[r] is a symbol s and the
  * output is (s, cdf[s], cdf[s+1]); mode 1 (decode) key[r] is a target count and the output is
  * the largest s with cdf[s] <= target, with its interval.  cdf: device rows x (vocab+1);

@@ -15,7 +15,7 @@ from ._lib import (NC_BF16, NC_F_ENSEMBLE, NC_F_HEAD, NC_F_MIXER, NC_F_NGRAM, NC
                    NC_FP32, NC_SKIP_ENTROPY, NC_SKIP_NONE, NC_SKIP_PMAX, NacrithError, NcConfig,
                    NcProbe, NcStats, check, lib)
 
-__all__ = ["quantize_cdf24", "cdf_interval", "encode_bound", "ac_encode", "ac_decode_static",
+__all__ = ["quantize_cdf24", "quantize_cdf24_noalloc", "cdf_interval", "encode_bound", "ac_encode", "ac_decode_static",
            "make_config", "Context", "NacrithError", "lib"]
 
 PRECISIONS = {"fp32": NC_FP32, "bf16": NC_BF16, "fp8": NC_FP8}
@@ -48,6 +48,23 @@ def quantize_cdf24(probs, total: int = 1 << 24, stream=None):
                                   _dev_ptr(cdf, torch.int32, "cdf"),
                                   _dev_ptr(st, torch.int32, "status"), _stream_ptr(stream)))
     return cdf, st
+
+
+def quantize_cdf24_noalloc(probs, cdf, status, total: int = 1 << 24, stream=None):
+    """nc_quantize_cdf24_noalloc into caller-allocated cdf (int32 [rows, V+1]) and status
+    (int32 [rows]) tensors: the library allocates nothing (its workspace is a fixed device
+    array shared by every call on the GPU)."""
+    import torch
+    if probs.dim() == 1:
+        probs = probs[None]
+    rows, v = probs.shape
+    if tuple(cdf.shape) != (rows, v + 1) or tuple(status.shape) != (rows,):
+        raise ValueError("cdf must be [rows, V+1] and status [rows]")
+    check(lib().nc_quantize_cdf24_noalloc(_dev_ptr(probs, torch.float32, "probs"), rows, v, total,
+                                          _dev_ptr(cdf, torch.int32, "cdf"),
+                                          _dev_ptr(status, torch.int32, "status"),
+                                          _stream_ptr(stream)))
+    return cdf, status
 
 
 def cdf_interval(cdf, keys, mode: int, stream=None):

@@ -71,6 +71,8 @@ _SIG = {
     "nc_probs_for_context": (C.c_int, [_P, C.c_uint32, _P, C.c_size_t, _P, C.POINTER(NcProbe)]),
     "nc_mix_update": (C.c_int, [_P, C.c_uint32, C.c_int32]),
     "nc_quantize_cdf24": (C.c_int, [_P, C.c_uint32, C.c_uint32, C.c_uint32, _P, _P, _P]),
+    "nc_quantize_cdf24_noalloc": (C.c_int, [_P, C.c_uint32, C.c_uint32, C.c_uint32, _P, _P,
+                                             _P]),
     "nc_cdf_interval": (C.c_int, [_P, C.c_uint32, C.c_uint32, _P, C.c_int32, _P, _P]),
     "nc_encode_stream": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P, _P, _P]),
     "nc_decode_stream": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P]),

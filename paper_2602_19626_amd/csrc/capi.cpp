@@ -65,6 +65,26 @@ nc_status nc_quantize_cdf24(const float* probs, uint32_t rows, uint32_t vocab, u
   });
 }
 
+nc_status nc_quantize_cdf24_noalloc(const float* probs, uint32_t rows, uint32_t vocab,
+                                    uint32_t total, uint32_t* cdf, int32_t* row_status,
+                                    void* stream) {
+  return guard([&] {
+    NC_CHECK(probs && cdf, NC_E_INVALID, "NULL pointer");
+    NC_CHECK(vocab >= 1 && vocab <= 262144u, NC_E_INVALID, "vocab must be in [1, 262144]");
+    NC_CHECK(total > vocab && total <= (1u << 24), NC_E_INVALID,
+             "total must satisfy vocab < total <= 2^24");
+    if (rows == 0) return;
+    const size_t need = quantize_workspace_needed(probs, rows, vocab);
+    NC_CHECK(need <= kScratchBytes, NC_E_CAPACITY,
+             "rows * ceil(vocab / 4096) = %zu segment partials exceed the %zu of the fixed "
+             "scratch array (the segment path runs for up to 64 rows, unaligned rows or "
+             "vocab > 49,152)", need / 16, kScratchParts);
+    launch_quantize_cdf(probs, rows, vocab, total, cdf, row_status,
+                        need ? quantize_scratch_address() : nullptr,
+                        static_cast<hipStream_t>(stream));
+  });
+}
+
 nc_status nc_cdf_interval(const uint32_t* cdf, uint32_t rows, uint32_t vocab, const uint32_t* key,
                           int32_t mode, uint32_t* out, void* stream) {
   return guard([&] {

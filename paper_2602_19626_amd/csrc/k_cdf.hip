@@ -1,5 +1,8 @@
 // CDF-24 quantise + scan over batches of probability rows (paper section 3.4) and the interval
 // lookup used by the arithmetic coder (section 3.9).
+#include <mutex>
+#include <unordered_map>
+
 #include "cdf_dev.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -258,14 +261,25 @@ size_t quantize_workspace_bytes(uint32_t rows, uint32_t V) {
   return size_t(rows) * ceil_div(V, kSeg) * sizeof(SegPartial);
 }
 
+// The row kernel places one workgroup per row, so a few rows leave most CUs idle; up to
+// kSegPathMaxRows rows the segment kernels (ceil(V / 4096) workgroups per row) finish sooner.
+// Both give the same integers.
+static bool vec_rows(const float* p, uint32_t V) {
+  return (V % 4 == 0) && (reinterpret_cast<uintptr_t>(p) % 16 == 0);
+}
+static bool use_row_kernel(const float* p, uint32_t rows, uint32_t V) {
+  return vec_rows(p, V) && V <= kRowMaxV && rows > kSegPathMaxRows;
+}
+
+size_t quantize_workspace_needed(const float* p, uint32_t rows, uint32_t V) {
+  return use_row_kernel(p, rows, V) ? 0 : quantize_workspace_bytes(rows, V);
+}
+
 void launch_quantize_cdf(const float* p, uint32_t rows, uint32_t V, uint32_t total, uint32_t* cdf,
                          int32_t* status, void* workspace, hipStream_t s) {
   if (rows == 0) return;
-  const bool vec = (V % 4 == 0) && (reinterpret_cast<uintptr_t>(p) % 16 == 0);
-  // The row kernel places one workgroup per row, so a few rows leave most CUs idle; up to
-  // kSegPathMaxRows rows the segment kernels (ceil(V / 4096) workgroups per row) finish sooner.
-  // Both give the same integers.
-  if (vec && V <= kRowMaxV && rows > kSegPathMaxRows) {
+  const bool vec = vec_rows(p, V);
+  if (use_row_kernel(p, rows, V)) {
     hipLaunchKernelGGL(cdf24_row_kernel, dim3(rows), dim3(kRowThreads), 0, s, p, V, total, cdf,
                        status);
     NC_HIP(hipGetLastError());
@@ -286,6 +300,28 @@ void launch_quantize_cdf(const float* p, uint32_t rows, uint32_t V, uint32_t tot
                        parts, cdf, status);
   }
   NC_HIP(hipGetLastError());
+}
+
+// Scratch of the no-allocation variant: the segment partials of up to kScratchParts segments
+// (1 MiB), one copy per device for the life of the process.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol); it passes the device
+// address that hipGetSymbolAddress resolves once per device.
+static_assert(sizeof(SegPartial) * kScratchParts == kScratchBytes, "scratch size");
+static __device__ __align__(256) SegPartial scratch[kScratchParts];
+
+void* quantize_scratch_address() {
+  static std::mutex mu;
+  static std::unordered_map<int, void*> addr;
+  int dev = 0;
+  NC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void* ptr = nullptr;
+  NC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  NC_CHECK(ptr != nullptr, NC_E_DEVICE, "no device address for the CDF-24 scratch array");
+  addr[dev] = ptr;
+  return ptr;
 }
 
 // mode 0: out = (s, cdf[s], cdf[s+1]) for s = key; mode 1: largest s with cdf[s] <= key.
