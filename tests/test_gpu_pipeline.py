@@ -139,3 +139,39 @@ def test_nc05_container_round_trip(setup):
     out = ct.decompress(ctx, blob)
     for a, b in zip(out, streams):
         assert np.array_equal(a, b)
+
+
+def test_nc06_hybrid_round_trip(setup):
+    """A mixed file (text with embedded control bytes, a large compressible binary block, random
+    binary bytes, short binary gaps) through NC06: text pieces coded as parallel GPU streams,
+    the binary blob by LZMA; the bytes come back exactly."""
+    _, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    from paper_2602_19626_amd import nc06
+    rng = np.random.default_rng(3)
+    words = [bytes(rng.integers(97, 123, rng.integers(2, 9), dtype=np.uint8)) for _ in range(60)]
+    zipf = 1.0 / np.arange(1, 61) ** 1.1
+
+    def text(n):
+        out = b""
+        while len(out) < n:
+            out += words[rng.choice(60, p=zipf / zipf.sum())] + (b"\n" if rng.random() < 0.1
+                                                                  else b" ")
+        return out[:n]
+    data = (text(900) + b"\x00\x01\x02" + text(500) + bytes(range(256)) * 24 + text(1300)
+            + bytes(rng.integers(0, 256, 700, dtype=np.uint8)) + text(40) + b"\xff" * 30)
+    seg = nc06.segment(data)
+    assert [k for k, _, _ in seg].count(nc06.TEXT) >= 2
+    cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32", skip=WL.skip,
+                         mix_init=WL.mix_init, max_streams=64)
+    ctx = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+    blob = nc06.compress(ctx, data, flags=7, max_chunk_tokens=600)
+    _, _, ents, codec, _, nraw = nc06.unpack(blob)
+    assert codec == nc06.LZMA and nraw >= nc06.LZMA_MIN_BLOB
+    texts = [e for e in ents if e.kind == nc06.TEXT]
+    assert len(texts) >= 4 and all(e.n_tokens <= 600 for e in texts)
+    assert nc06.decompress(ctx, blob) == data
+    assert len(blob) < len(data)
+    # each text entry's stream is what the pipeline codes for that piece alone
+    piece = data[seg[0][1]:seg[0][1] + texts[0].n_bytes]
+    assert ctx.encode_stream([nc06.tokens_of(piece)])[0][0] == texts[0].data
