@@ -97,10 +97,11 @@ def traffic_from(fetch_csv: str, write_csv: str, kernel: str, workload: str, pro
     return t
 
 
-def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024), reps: int = 20):
+def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024, 4096), reps: int = 20):
     """nc_quantize_cdf24 alone on float32 rows of softmax-shaped probabilities (up to 64 rows the
     segment reduce + scan kernels, more rows the one-workgroup-per-row kernel); algorithmic bytes
-    per row = read 4V + write 4(V + 1)."""
+    per row = read 4V + write 4(V + 1).  From 1,024 rows at V = 49,152 the rows and their CDFs
+    (402 MB and more) exceed the 256 MB Infinity Cache."""
     out = []
     g = torch.Generator(device="cuda").manual_seed(5)
     for rows in rows_list:
@@ -169,23 +170,99 @@ def ablation(nc, wl, weights, streams, n_oracle: int):
     return rows
 
 
-def cpu_baseline(wl, weights, stream, n_sample: int):
-    """The oracle (FP64 numpy + exact integer quantiser + Python-integer coder) on a prefix."""
-    from threadpoolctl import threadpool_info
+def cpu_baseline(wl, weights, stream, n_sample: int, n_single: int):
+    """The oracle (FP64 numpy + exact integer quantiser + Python-integer coder) on a prefix, with
+    every BLAS thread, and again on a shorter prefix with one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import pipeline as op
     s = op.Settings.from_workload(wl)
+
+    def run(toks):
+        t0 = time.perf_counter()
+        r = op.encode(s, wl.shape, weights, toks)
+        t1 = time.perf_counter()
+        out = op.decode(s, wl.shape, weights, r.data, len(toks))
+        t2 = time.perf_counter()
+        assert np.array_equal(out, toks), "oracle round trip failed"
+        return r, t1 - t0, t2 - t1
+
     toks = stream[:n_sample]
-    t0 = time.perf_counter()
-    r = op.encode(s, wl.shape, weights, toks)
-    t1 = time.perf_counter()
-    out = op.decode(s, wl.shape, weights, r.data, len(toks))
-    t2 = time.perf_counter()
-    assert np.array_equal(out, toks), "oracle round trip failed"
+    r, te, td = run(toks)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return r, {"value": round(len(toks) / (t2 - t0), 3), "unit": "tokens/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"first {len(toks)} tokens of stream 0, encode ({t1 - t0:.1f} s) + "
-                         f"decode ({t2 - t1:.1f} s), FP64 numpy with {threads} BLAS threads"}
+    out = {"value": round(len(toks) / (te + td), 3), "unit": "tokens/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"first {len(toks)} tokens of stream 0 (the KV cache slides at token 2,048), "
+                     f"encode ({te:.1f} s) + decode ({td:.1f} s), FP64 numpy with {threads} "
+                     "BLAS threads"}
+    if n_single:
+        with threadpool_limits(limits=1):
+            t1 = stream[:n_single]
+            _, te1, td1 = run(t1)
+        out["single_thread"] = {"value": round(len(t1) / (te1 + td1), 3), "unit": "tokens/s",
+                                "cores": 1, "sample": f"first {len(t1)} tokens, encode "
+                                f"({te1:.1f} s) + decode ({td1:.1f} s), one BLAS thread"}
+    return r, out
+
+
+def class_rooflines(prof: dict, precision: str) -> dict:
+    """Per kernel class: average launch time and the achieved fraction of its roofline (HBM for
+    byte-bound classes, MFMA for classes whose arithmetic intensity is above the ridge)."""
+    ridge = MFMA_PEAK_TFLOPS[precision] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    out = {}
+    for cls, k in prof.items():
+        if not k["timed"]:
+            continue
+        ai = k["flops"] / max(k["bytes"], 1.0)
+        mfma = cls in ("qkv", "oproj", "gateup", "down", "lmhead", "attn") and ai > ridge
+        if mfma:
+            ach, peak, unit = k["flops"] / k["ms"] / 1e9, MFMA_PEAK_TFLOPS[precision], "TFLOP/s"
+        else:
+            ach, peak, unit = k["bytes"] / k["ms"] / 1e6, HBM_PEAK_GBS, "GB/s"
+        out[cls] = {"bound": "mfma" if mfma else "hbm", "achieved": round(ach, 2), "peak": peak,
+                    "unit": unit, "frac": round(ach / peak, 4),
+                    "avg_launch_us": round(1000 * k["ms"] / k["timed"], 3),
+                    "launches": k["launches"], "timed_launches": k["timed"],
+                    "est_total_ms": round(k["ms"] * k["launches"] / k["timed"], 1),
+                    "algorithmic_bytes_per_launch": round(k["bytes"] / k["timed"]),
+                    "algorithmic_flops_per_launch": round(k["flops"] / k["timed"])}
+    return out
+
+
+def batched_line(nc, synth, max_len: int, steps: int = 1):
+    """The 64-stream BF16 workload (p_max skip) with every stream cut to max_len tokens:
+    encode + decode tokens/s, round trip checked."""
+    wl = synth.WORKLOADS["batch64_bf16"]
+    streams = synth.workload_streams(wl, max_len=max_len)
+    n_tok = int(sum(len(s) for s in streams))
+    w = synth.make_weights(wl.shape, wl.weight_seed)
+    cfg = nc.make_config(wl.shape, ngram_order=wl.ngram_order, precision=wl.precision,
+                         skip=wl.skip, mix_init=wl.mix_init, warmup=wl.warmup, head_lr=wl.head_lr,
+                         cdf_total=wl.cdf_total, max_streams=len(streams))
+    ctx = nc.Context(cfg, synth.flat_weights(wl.shape, w))
+    ctx.autotune(max_rows=len(streams) * wl.shape.slide, reps=5)
+    data, _ = ctx.encode_stream(streams)              # warm-up
+    ctx.decode_stream(data, [len(s) for s in streams])
+    te = td = 0.0
+    ok = True
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        data, bits = ctx.encode_stream(streams)
+        t1 = time.perf_counter()
+        out = ctx.decode_stream(data, [len(s) for s in streams])
+        t2 = time.perf_counter()
+        te += t1 - t0
+        td += t2 - t1
+        ok = ok and all(np.array_equal(a, b) for a, b in zip(out, streams))
+    st = ctx.stats()
+    ctx.close()
+    return {"workload": f"batch64_bf16, every stream cut to {max_len} tokens",
+            "streams": len(streams), "tokens": n_tok,
+            "value": round(steps * n_tok / (te + td), 1),
+            "encode_tok_s": round(steps * n_tok / te, 1),
+            "decode_tok_s": round(steps * n_tok / td, 1),
+            "bits_per_token": round(float(sum(bits)) / n_tok, 5),
+            "skip_rate": round(st["skipped"] / max(st["tokens"], 1), 4),
+            "roundtrip_exact": bool(ok)}
 
 
 def main():
@@ -194,10 +271,14 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="full_fp32")
-    ap.add_argument("--kernel", default="attn", help="kernel class for the roofline")
+    ap.add_argument("--kernel", default="auto",
+                    help="kernel class for the roofline (auto: the class with the most time)")
     ap.add_argument("--max-len", type=int, default=None, help="truncate streams (quick runs)")
     ap.add_argument("--n-streams", type=int, default=None)
-    ap.add_argument("--cpu-sample", type=int, default=1500)
+    ap.add_argument("--cpu-sample", type=int, default=2200,
+                    help="oracle prefix (all BLAS threads); the default crosses the KV slide")
+    ap.add_argument("--cpu-single-sample", type=int, default=256,
+                    help="oracle prefix timed with one BLAS thread (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain streaming kernel of this size first (counter scaling)")
@@ -207,8 +288,12 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="run the A0-A4 feature ladder on the workload instead of the timing")
     ap.add_argument("--oracle-prefix", type=int, default=200)
-    ap.add_argument("--profile-stride", type=int, default=8,
-                    help="time every n-th launch of the roofline class with HIP events")
+    ap.add_argument("--profile-stride", type=int, default=4,
+                    help="in the profiled step after the timed ones, time every n-th launch of "
+                         "each kernel class with HIP events")
+    ap.add_argument("--batch-len", type=int, default=2048,
+                    help="also run the 64-stream BF16 workload cut to this many tokens per "
+                         "stream (0 = skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the fixed GEMM launch-shape rule (no tuning before the warmup)")
     args = ap.parse_args()
@@ -277,7 +362,6 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    ctx.profile(args.kernel, args.profile_stride)
     t_enc = t_dec = w_enc = w_dec = 0.0
     ok = True
     for _ in range(args.steps):
@@ -287,29 +371,26 @@ def main():
         w_enc += st_enc["wait_seconds"]
         w_dec += st_dec["wait_seconds"]
         ok = ok and all(np.array_equal(a, b) for a, b in zip(out, streams))
-    prof = ctx.profile_read()
-    ctx.profile(None)
     total_bits = float(sum(bits))
+    ideal_enc = st_enc["ideal_bits"]
+    skip_rate = st_dec["skipped"] / max(st_dec["tokens"], 1)
 
-    # roofline of the profiled kernel class
-    avg_ms = prof["ms"] / max(prof["timed"], 1)
-    gemm_classes = ("qkv", "oproj", "gateup", "down", "lmhead")
-    bound = "hbm"
-    achieved = prof["bytes"] / max(prof["ms"], 1e-9) / 1e6           # GB/s
-    peak, unit = HBM_PEAK_GBS, "GB/s"
-    ai = prof["flops"] / max(prof["bytes"], 1.0)
-    ridge = MFMA_PEAK_TFLOPS[wl.precision] * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if args.kernel in gemm_classes + ("attn",) and ai > ridge:
-        bound = "mfma"
-        achieved = prof["flops"] / max(prof["ms"], 1e-9) / 1e9        # TFLOP/s
-        peak, unit = MFMA_PEAK_TFLOPS[wl.precision], "TFLOP/s"
-    traffic = load_traffic(args.kernel, args.workload)
-    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": args.kernel, "launches": prof["launches"],
-                "timed_launches": prof["timed"], "avg_launch_us": round(avg_ms * 1000, 3),
-                "algorithmic_bytes_per_launch": round(prof["bytes"] / max(prof["timed"], 1)),
-                "algorithmic_flops_per_launch": round(prof["flops"] / max(prof["timed"], 1))}
+    # one more step, untimed, with every kernel class bracketed by HIP events on its stream
+    ctx.profile("all", args.profile_stride)
+    step()
+    from paper_2602_19626_amd._lib import KERNEL_CLASSES
+    prof = {k: ctx.profile_read(k) for k in KERNEL_CLASSES}
+    ctx.profile(None)
+    classes = class_rooflines(prof, wl.precision)
+    kern = args.kernel if args.kernel != "auto" else \
+        max(classes, key=lambda k: classes[k]["est_total_ms"])
+    roofline = dict(classes[kern])
+    roofline["kernel"] = kern
+    roofline["traffic"] = load_traffic(kern, args.workload)
+    roofline = {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                         "kernel", "avg_launch_us", "launches", "timed_launches",
+                                         "algorithmic_bytes_per_launch",
+                                         "algorithmic_flops_per_launch")}
 
     line = {"metric": METRIC,
             "value": round(args.steps * n_tok / (t_enc + t_dec), 2),
@@ -325,17 +406,20 @@ def main():
             "encode_tok_s": round(args.steps * n_tok / t_enc, 2),
             "decode_tok_s": round(args.steps * n_tok / t_dec, 2),
             "bits_per_token": round(total_bits / n_tok, 5),
-            "skip_rate": None, "roundtrip_exact": bool(ok),
+            "skip_rate": round(skip_rate, 4), "roundtrip_exact": bool(ok),
             "host_wait_frac": {"encode": round(w_enc / t_enc, 3), "decode": round(w_dec / t_dec, 3)},
-            "roofline": roofline, "autotune": tune}
+            "roofline": roofline, "kernel_classes": classes, "autotune": tune}
     line["cdf24_standalone"] = cdf24_standalone(nc, torch, wl.shape.vocab)
-    dstat = ctx.stats()
-    line["skip_rate"] = round(dstat["skipped"] / max(dstat["tokens"], 1), 4)
-    line["gpu_ideal_bits_per_token"] = round(st_enc["ideal_bits"] / n_tok, 5)
+    line["gpu_ideal_bits_per_token"] = round(ideal_enc / n_tok, 5)
+    if args.batch_len and args.workload == "full_fp32":
+        b = batched_line(nc, synth, args.batch_len)
+        b["vs_this_line_value"] = round(b["value"] / line["value"], 2)
+        line["batch64_bf16"] = b
 
     if not args.no_cpu_baseline:
         n_s = min(args.cpu_sample, len(streams[0]))
-        ref, cb = cpu_baseline(wl, weights, streams[0], n_s)
+        ref, cb = cpu_baseline(wl, weights, streams[0], n_s,
+                               min(args.cpu_single_sample, len(streams[0])))
         line["cpu_baseline"] = cb
         # gap of the GPU coder against the oracle's ideal code length, same prefix
         d, b = ctx.encode_stream([streams[0][:n_s]])

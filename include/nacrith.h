@@ -228,13 +228,15 @@ typedef struct nc_kstat {
   double flops;       /* algorithmic flops of the timed launches */
 } nc_kstat;
 
-/* Select the profiled kernel class (-1 = off) and clear its counters.  Every stride-th launch
- * of the class (stride >= 1) is bracketed by events, which bounds the cost of the event records
- * on long runs; ms / timed is the class's average launch duration.  NC_E_INVALID for a bad class
- * or stride 0. */
+/* Enable timing of one kernel class (0 .. NC_K_COUNT-1), or of every class (NC_K_COUNT), and
+ * clear its counters; -1 disables and clears every class.  Classes enabled by earlier calls stay
+ * enabled.  Every stride-th launch of a class (stride >= 1) is bracketed by events recorded on the
+ * stream the class runs on, which bounds the cost of the event records on long runs; ms / timed
+ * is the class's average launch duration.  The events add work to the stream, so runs whose wall
+ * time is reported should not profile.  NC_E_INVALID for a bad class or stride 0. */
 nc_status nc_profile(nc_ctx* ctx, int32_t kernel_class, uint32_t stride);
-/* Counters of the profiled class since nc_profile(). */
-nc_status nc_profile_read(nc_ctx* ctx, nc_kstat* out);
+/* Counters of one kernel class since it was enabled. */
+nc_status nc_profile_read(nc_ctx* ctx, int32_t kernel_class, nc_kstat* out);
 
 /* ---- launch-shape autotuner ------------------------------------------------------------------
  * Each transformer GEMM can run in several launch shapes: a split kernel (one workgroup per

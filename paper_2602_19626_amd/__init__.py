@@ -233,16 +233,17 @@ class Context:
         check(lib().nc_tiles_reset(self._h))
 
     def profile(self, kernel_class, stride: int = 1):
-        """Time every stride-th launch of one kernel class with HIP events on the library's
-        stream (None = off)."""
-        from ._lib import KERNEL_CLASSES
-        cls = -1 if kernel_class is None else KERNEL_CLASSES[kernel_class]
+        """Time every stride-th launch of a kernel class ("all" = every class; None = off) with
+        HIP events on the stream the class runs on."""
+        from ._lib import ALL_KERNEL_CLASSES, KERNEL_CLASSES
+        cls = -1 if kernel_class is None else (
+            ALL_KERNEL_CLASSES if kernel_class == "all" else KERNEL_CLASSES[kernel_class])
         check(lib().nc_profile(self._h, cls, int(stride)))
 
-    def profile_read(self) -> dict:
-        from ._lib import NcKstat
+    def profile_read(self, kernel_class) -> dict:
+        from ._lib import KERNEL_CLASSES, NcKstat
         k = NcKstat()
-        check(lib().nc_profile_read(self._h, C.byref(k)))
+        check(lib().nc_profile_read(self._h, KERNEL_CLASSES[kernel_class], C.byref(k)))
         return {f: getattr(k, f) for f, _ in NcKstat._fields_}
 
     def stats(self) -> dict:

@@ -59,6 +59,7 @@ class NcKstat(C.Structure):
 
 KERNEL_CLASSES = {"qkv": 0, "attn": 1, "oproj": 2, "gateup": 3, "down": 4, "lmhead": 5,
                   "vocab": 6, "ngram": 7}
+ALL_KERNEL_CLASSES = 8
 
 _P = C.c_void_p
 _SIG = {
@@ -82,7 +83,7 @@ _SIG = {
                               C.POINTER(C.c_uint32)]),
     "nc_tiles_reset": (C.c_int, [_P]),
     "nc_tiles_set": (C.c_int, [_P, C.c_void_p, C.c_uint32]),
-    "nc_profile_read": (C.c_int, [_P, C.POINTER(NcKstat)]),
+    "nc_profile_read": (C.c_int, [_P, C.c_int32, C.POINTER(NcKstat)]),
     "nc_ac_encode": (C.c_int, [_P, C.c_size_t, C.c_uint32, _P, C.c_size_t, _P, _P]),
     "nc_ac_decode_static": (C.c_int, [_P, C.c_size_t, _P, C.c_uint32, C.c_size_t, _P]),
     "nc_ensemble_forward": (C.c_int, [_P, _P, _P, _P, _P, C.c_uint32, C.c_uint32, C.c_uint32,

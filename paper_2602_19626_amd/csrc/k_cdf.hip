@@ -78,37 +78,31 @@ __global__ __launch_bounds__(kSegThreads) void cdf24_scan_kernel(
   }
 }
 
-// One workgroup per row for V <= 49,152 (768 threads; thread t owns entries 3072 q + 4 t .. + 3,
-// q < 16).  The row is read once into registers (64 floats per thread).  From them the kernel
-// reduces the floor counts, the lowest-index argmax and the validity; one barrier round scans all
-// sixteen 3072-entry blocks at once (a wave scan per block, block and wave offsets by a two-level
-// scan of the wave totals in LDS); the CDF is then written from the registers with the widest
-// stores the row's alignment allows.  Every result is an integer or a comparison, so it equals the
+// One workgroup per row for V <= 49,152, several rows resident per CU.  512 threads; thread t owns
+// the four entries 2048 q + 4 t .. + 3 of each 2048-entry block q < 24.  Pass 1 reads the row and
+// reduces the floor counts (each thread's four-entry sums are kept in LDS), the lowest-index
+// argmax and the validity; one barrier round turns the sums into the CDF value before every
+// thread's first entry of every block (a wave scan per block, block and wave offsets by a
+// two-level scan of the wave totals).  Pass 2 reads the row again (a row read moments before, so
+// it comes from the caches), recomputes each entry's count and writes the CDF with the widest
+// stores the row's alignment allows.  The kernel holds no row in registers: its 48 KiB of LDS and
+// few registers let three rows overlap on a CU, so one row's loads, another's scan and a third's
+// stores keep the memory busy.  Every result is an integer or a comparison, so it equals the
 // two-kernel result.
 typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));
-constexpr int kRowThreads = 768;
+constexpr int kRowThreads = 512;
 constexpr int kRowWaves = kRowThreads / 64;
-constexpr int kRowBlocks = 16;
-constexpr int kRowBlock = kRowThreads * 4;  // 3072 entries
+constexpr int kRowBlock = kRowThreads * 4;  // 2048 entries
+constexpr int kRowBlocks = 24;
+constexpr int kRowBatch = 8;                // loads in flight per thread
 constexpr uint32_t kRowMaxV = kRowBlocks * kRowBlock;
 constexpr uint32_t kSegPathMaxRows = 64;
 
-__device__ __forceinline__ void row_load4(const float* p, uint32_t i0, uint32_t V, float (&x)[4]) {
-  if (i0 + 3 < V) {
-    const f4v q = *reinterpret_cast<const f4v*>(p + i0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = q[i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = i0 + i < V ? p[i0 + i] : 0.f;
-  }
-}
-
-__global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __restrict__ probs,
-                                                                 uint32_t V, uint32_t total,
-                                                                 uint32_t* __restrict__ cdf,
-                                                                 int32_t* __restrict__ status) {
+__global__ __launch_bounds__(kRowThreads, 6) void cdf24_row_kernel(const float* __restrict__ probs,
+                                                                   uint32_t V, uint32_t total,
+                                                                   uint32_t* __restrict__ cdf,
+                                                                   int32_t* __restrict__ status) {
   __shared__ uint64_t s_sum[kRowWaves];
   __shared__ float s_best[kRowWaves];
   __shared__ uint32_t s_bi[kRowWaves];
@@ -116,42 +110,45 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
   __shared__ uint32_t s_wt[kRowWaves][kRowBlocks];
   __shared__ uint32_t s_bt[kRowBlocks];
   __shared__ uint32_t s_off[kRowWaves][kRowBlocks];
-  // per (block, thread): the 4-entry count sum, then its exclusive prefix within the wave
+  // per (block, thread): the four-entry count sum, then its exclusive prefix within the wave
   __shared__ uint32_t s_cnt[kRowBlocks][kRowThreads];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t row = blockIdx.x;
   const float* p = probs + size_t(row) * V;
-  const uint32_t m = total - V;
-  // the whole row in registers: every load is issued before the first use (V % 4 == 0, so a
-  // group of four is either whole or past the end)
-  float x[kRowBlocks][4];
   const f4v* p4 = reinterpret_cast<const f4v*>(p) + tid;
-#pragma unroll
-  for (int q = 0; q < kRowBlocks; ++q) {
-    const f4v v = q * kRowBlock + 4 * tid < V ? p4[q * kRowThreads] : f4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x[q][i] = v[i];
-  }
+  const uint32_t m = total - V;
+  // pass 1 (V % 4 == 0: a group of four is either whole or past the end)
   uint64_t sum = 0;
   float best = -1.f;
   uint32_t bi = 0xFFFFFFFFu;
   int bad = 0;
+#pragma unroll 1
+  for (int q0 = 0; q0 < kRowBlocks; q0 += kRowBatch) {
+    f4v x[kRowBatch];
 #pragma unroll
-  for (int q = 0; q < kRowBlocks; ++q) {
-    const uint32_t i0 = q * kRowBlock + 4 * tid;
-    uint32_t c4 = 0;
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int q = q0 + u;
+      x[u] = q * kRowBlock + 4 * tid < V ? p4[q * kRowThreads] : f4v{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (i0 + i < V) {
-        if (!(x[q][i] >= 0.f && x[q][i] <= 1.f)) bad = 1;
-        c4 += floor_count(x[q][i], m);
-        if (x[q][i] > best) {
-          best = x[q][i];
-          bi = i0 + i;
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int q = q0 + u;
+      const uint32_t i0 = q * kRowBlock + 4 * tid;
+      uint32_t c4 = 0;
+      if (i0 < V) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (!(x[u][i] >= 0.f && x[u][i] <= 1.f)) bad = 1;
+          c4 += floor_count(x[u][i], m);
+          if (x[u][i] > best) {
+            best = x[u][i];
+            bi = i0 + i;
+          }
         }
       }
-    s_cnt[q][tid] = c4;
-    sum += c4;
+      s_cnt[q][tid] = c4;
+      sum += c4;
+    }
   }
   sum = wave_sum_u64(sum);
   wave_argmax(best, bi);
@@ -182,8 +179,7 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
     if (!rq.status && int64_t(floor_count(bv, m)) + r < 1) rq.status = 1;
     rq.start = 0;
   }
-  // the residual belongs to the argmax entry (corrected_count); per-block wave scans, the
-  // lane-exclusive prefixes parked in LDS to keep registers for the row
+  // the residual belongs to the argmax entry (corrected_count); per-block wave scans
 #pragma unroll
   for (int q = 0; q < kRowBlocks; ++q) {
     const uint32_t i0 = q * kRowBlock + 4 * tid;
@@ -220,21 +216,30 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
     out[0] = 0;
     if (status) status[row] = rq.status;
   }
-  // entries 3072 q + 4 t + i go to out[1 + 3072 q + 4 t + i]; every such group of four starts at
-  // the same word phase within the row
+  // pass 2: entries 2048 q + 4 t + i go to out[1 + 2048 q + 4 t + i]; every such group of four
+  // starts at the same word phase within the row
   const uint32_t phase = uint32_t((reinterpret_cast<uintptr_t>(out + 1) >> 2) & 3);
+#pragma unroll 1
+  for (int q0 = 0; q0 < kRowBlocks; q0 += kRowBatch) {
+    f4v x[kRowBatch];
 #pragma unroll
-  for (int q = 0; q < kRowBlocks; ++q) {
-    const uint32_t i0 = q * kRowBlock + 4 * tid;
-    if (i0 >= V) continue;
-    uint32_t r4[4], run = s_off[w][q] + s_cnt[q][tid];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      run += i0 + i < V ? corrected_count(x[q][i], i0 + i, rq) : 0u;
-      r4[i] = run;
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int q = q0 + u;
+      x[u] = q * kRowBlock + 4 * tid < V ? __builtin_nontemporal_load(p4 + q * kRowThreads)
+                                         : f4v{0.f, 0.f, 0.f, 0.f};
     }
-    uint32_t* dst = out + 1 + i0;
-    if (i0 + 3 < V) {
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int q = q0 + u;
+      const uint32_t i0 = q * kRowBlock + 4 * tid;
+      if (i0 >= V) continue;
+      uint32_t r4[4], run = s_off[w][q] + s_cnt[q][tid];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        run += corrected_count(x[u][i], i0 + i, rq);
+        r4[i] = run;
+      }
+      uint32_t* dst = out + 1 + i0;
       if (phase == 0) {
         __builtin_nontemporal_store(u4v{r4[0], r4[1], r4[2], r4[3]}, reinterpret_cast<u4v*>(dst));
       } else if (phase == 2) {
@@ -249,10 +254,6 @@ __global__ __launch_bounds__(kRowThreads) void cdf24_row_kernel(const float* __r
         dst[1] = r4[1];
         __builtin_nontemporal_store(u2v{r4[2], r4[3]}, reinterpret_cast<u2v*>(dst + 2));
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (i0 + i < V) dst[i] = r4[i];
     }
   }
 }

@@ -139,15 +139,18 @@ struct nc_ctx {
   std::vector<int> appended;                // x positions in the KV cache per stream
   nc_stats stats{};
   VocabParams vp{};
-  // measurement: events around launches of one kernel class
-  int prof_class = -1;
-  uint32_t prof_stride = 1;   // time every prof_stride-th launch of the class
-  uint64_t prof_seen = 0;     // launches of the class since nc_profile
-  bool prof_open = false;     // the current launch is being timed
-  nc_kstat prof{};
+  // measurement: events around the launches of the enabled kernel classes
+  struct ProfClass {
+    bool on = false;
+    uint32_t stride = 1;   // time every stride-th launch of the class
+    uint64_t seen = 0;     // launches of the class since it was enabled
+    bool open = false;     // the current launch is being timed
+    hipEvent_t ev_open = nullptr;
+    nc_kstat k{};
+  };
+  ProfClass prof[NC_K_COUNT];
   std::vector<hipEvent_t> ev_free;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_busy;
-  hipEvent_t ev_open = nullptr;
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev_busy;  // (events, class)
   // measured GEMM launch shapes per (GEMM, row bucket); kind T_AUTO = the fixed rule
   GemmTile tiles[NC_G_COUNT][kRowBuckets];
 
@@ -185,8 +188,8 @@ nc_ctx::~nc_ctx() {
   dstage.release();
   for (auto e : ev_free) (void)hipEventDestroy(e);
   for (auto& pr : ev_busy) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
+    (void)hipEventDestroy(pr.first.first);
+    (void)hipEventDestroy(pr.first.second);
   }
   for (hipEvent_t e : {ev_dist[0], ev_dist[1], ev_pred})
     if (e) (void)hipEventDestroy(e);
@@ -228,10 +231,10 @@ hipEvent_t take_event(nc_ctx* c) {
 void prof_flush(nc_ctx* c) {
   for (auto& pr : c->ev_busy) {
     float ms = 0.f;
-    NC_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-    c->prof.ms += ms;
-    c->ev_free.push_back(pr.first);
-    c->ev_free.push_back(pr.second);
+    NC_HIP(hipEventElapsedTime(&ms, pr.first.first, pr.first.second));
+    c->prof[pr.second].k.ms += ms;
+    c->ev_free.push_back(pr.first.first);
+    c->ev_free.push_back(pr.first.second);
   }
   c->ev_busy.clear();
 }
@@ -247,23 +250,25 @@ void sync(nc_ctx* c) {
 
 // Bracket the launches of one kernel class; bytes / flops are the launch's algorithmic work.
 void prof_begin(nc_ctx* c, int cls, hipStream_t s = nullptr) {
-  if (cls != c->prof_class) return;
-  c->prof_open = c->prof_seen++ % c->prof_stride == 0;
-  if (!c->prof_open) return;
-  c->ev_open = take_event(c);
-  NC_HIP(hipEventRecord(c->ev_open, s ? s : c->st));
+  auto& P = c->prof[cls];
+  if (!P.on) return;
+  P.open = P.seen++ % P.stride == 0;
+  if (!P.open) return;
+  P.ev_open = take_event(c);
+  NC_HIP(hipEventRecord(P.ev_open, s ? s : c->st));
 }
 void prof_end(nc_ctx* c, int cls, double bytes, double flops, hipStream_t s = nullptr) {
-  if (cls != c->prof_class) return;
-  c->prof.launches += 1;
-  if (!c->prof_open) return;
-  c->prof_open = false;
+  auto& P = c->prof[cls];
+  if (!P.on) return;
+  P.k.launches += 1;
+  if (!P.open) return;
+  P.open = false;
   hipEvent_t e = take_event(c);
   NC_HIP(hipEventRecord(e, s ? s : c->st));
-  c->ev_busy.emplace_back(c->ev_open, e);
-  c->prof.timed += 1;
-  c->prof.bytes += bytes;
-  c->prof.flops += flops;
+  c->ev_busy.push_back({{P.ev_open, e}, cls});
+  P.k.timed += 1;
+  P.k.bytes += bytes;
+  P.k.flops += flops;
   if (c->ev_busy.size() > 4096) sync(c);
 }
 
@@ -440,15 +445,15 @@ PassPlan plan_pass(nc_ctx* c, std::vector<RowMeta> rows, bool calib = false) {
         it.c0 = c0;
         it.ncols = std::min(16, nq * g - c0);
         p.items.push_back(it);
-        // algorithmic work: the item's window keys/values read once, q in, o out
-        const int p0 = it.pos_base + it.c0 / g, p1 = it.pos_base + (it.c0 + it.ncols - 1) / g;
-        p.attn_bytes += double(p1 - wstart(p0) + 1) * c->hd * 2 * esa +
-                        it.ncols * double(c->hd) * (esa + eso);
         for (int cc = 0; cc < it.ncols; ++cc) {
           const int q = it.pos_base + (it.c0 + cc) / g;
           p.attn_flops += 4.0 * double(q - wstart(q) + 1) * c->hd;
         }
       }
+    // algorithmic bytes of the run: the union of its rows' windows, [s(first), last], read once
+    // per kv head (K and V), the queries in and the outputs out
+    p.attn_bytes += double(c->hk) * double(R[j].pos - wstart(R[i].pos) + 1) * c->hd * 2 * esa +
+                    double(nq) * c->hq * c->hd * (esa + eso);
     src.push_back(j);
     dst.push_back(R[j].stream);
     i = j + 1;
@@ -1445,15 +1450,17 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
 nc_status nc_profile(nc_ctx* c, int32_t cls, uint32_t stride) {
   return guard([&] {
     NC_CHECK(c, NC_E_INVALID, "NULL context");
-    NC_CHECK(cls >= -1 && cls < NC_K_COUNT, NC_E_INVALID, "bad kernel class");
+    NC_CHECK(cls >= -1 && cls <= NC_K_COUNT, NC_E_INVALID, "bad kernel class");
     NC_CHECK(stride >= 1, NC_E_INVALID, "stride must be >= 1");
     NC_HIP(hipSetDevice(c->dev));
     sync(c);
-    c->prof_class = cls;
-    c->prof_stride = stride;
-    c->prof_seen = 0;
-    c->prof_open = false;
-    c->prof = nc_kstat{};
+    for (int k = 0; k < NC_K_COUNT; ++k) {
+      if (cls != -1 && cls != NC_K_COUNT && cls != k) continue;
+      auto& P = c->prof[k];
+      P = nc_ctx::ProfClass{};
+      P.on = cls != -1;
+      P.stride = stride;
+    }
   });
 }
 
@@ -1606,12 +1613,13 @@ nc_status nc_tiles_reset(nc_ctx* c) {
   });
 }
 
-nc_status nc_profile_read(nc_ctx* c, nc_kstat* out) {
+nc_status nc_profile_read(nc_ctx* c, int32_t cls, nc_kstat* out) {
   return guard([&] {
     NC_CHECK(c && out, NC_E_INVALID, "NULL argument");
+    NC_CHECK(cls >= 0 && cls < NC_K_COUNT, NC_E_INVALID, "bad kernel class");
     NC_HIP(hipSetDevice(c->dev));
     sync(c);
-    *out = c->prof;
+    *out = c->prof[cls].k;
   });
 }
 

@@ -153,3 +153,43 @@ def test_two_streams_do_not_share_a_workspace(nc):
             assert np.array_equal(ca[r].astype(np.int64), quantize_cdf(a[r])), r
         for r in range(0, 40, 5):
             assert np.array_equal(cb[r].astype(np.int64), quantize_cdf(b[r])), r
+
+
+def _adversarial(v, rng):
+    rows = []
+    p = rng.dirichlet(np.full(v, 0.05)).astype(np.float32)
+    p[[10, v // 2 + 3]] = p.max()                   # tie for the maximum: lowest index wins
+    rows.append(p / np.float32(p.sum()))
+    rows.append(rng.dirichlet(np.full(v, 0.5)).astype(np.float32) * np.float32(1.00001))
+    z = np.zeros(v, np.float32)
+    z[[0, v - 1]] = 0.5
+    rows.append(z)
+    s = rng.dirichlet(np.full(v, 0.05)).astype(np.float32)
+    s[::7] = np.float32(1e-40)
+    rows.append(s)
+    t = np.full(v, np.float32(1.0 / v))
+    t[v // 3] = np.nextafter(t[v // 3], np.float32(1))
+    rows.append(t)
+    oh = np.zeros(v, np.float32)
+    oh[v - 2] = 1.0
+    rows.append(oh)
+    return rows
+
+
+@pytest.mark.parametrize("v", [512, 2048, 4100, 12288, 49148, 49152])
+def test_row_kernel_path_adversarial_and_ragged(nc, v):
+    """More than 64 rows of a vocabulary that is a multiple of 4 run the one-workgroup-per-row
+    kernel: adversarial rows (ties, mass above one, subnormals, near-integer products, one-hot)
+    and random rows, bit-exact with the oracle; invalid rows are flagged."""
+    rng = np.random.default_rng(v)
+    rows = _adversarial(v, rng)
+    while len(rows) < 70:
+        rows.append(rng.dirichlet(np.full(v, rng.choice([0.01, 0.3, 3.0]))).astype(np.float32))
+    rows = np.stack(rows)
+    _check(nc, rows)
+    bad = rows.copy()
+    bad[3, 5] = np.nan
+    bad[40, 6] = -1e-3
+    bad[69, :] = 1.0
+    _, st = _gpu_cdf(nc, bad)
+    assert [r for r in range(70) if st[r]] == [3, 40, 69]
