@@ -47,7 +47,9 @@ enum {
   NC_F_NGRAM = 1u << 1,     /* token n-gram, section 3.5 */
   NC_F_SKIP = 1u << 2,      /* confidence-based LLM skip, section 3.8 */
   NC_F_MIXER = 1u << 3,     /* linear context mixer, section 3.6 */
-  NC_F_ENSEMBLE = 1u << 4   /* softmax-gated {LLM, n-gram orders 1..K} head trained by SGD */
+  NC_F_ENSEMBLE = 1u << 4,  /* softmax-gated {LLM, n-gram orders 1..K} head trained by SGD */
+  NC_F_EAGER = 1u << 5      /* launch every kernel of a decode / probe transformer pass directly
+                               instead of replaying a captured HIP graph of the pass (same bits) */
 };
 enum { NC_MODE_LLM = 0, NC_MODE_SKIP = 1, NC_MODE_MIX = 2, NC_MODE_ENSEMBLE = 3 };
 
@@ -99,6 +101,8 @@ typedef struct nc_stats {
   double ideal_bits;         /* sum -log2 p_i(t_i) of the float32 coding distributions */
   double seconds;            /* wall time of the call */
   double wait_seconds;       /* part of it the host spent blocked on the device */
+  uint64_t graph_replays;    /* transformer passes run by replaying a captured HIP graph */
+  uint64_t graph_captures;   /* passes captured (first use of a pass shape) */
 } nc_stats;
 
 typedef struct nc_ctx nc_ctx;

@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "NC_OK", 1: "NC_E_INVALID", 2: "NC_E_DEVICE", 3: "NC_E_NOMEM"
                 4: "NC_E_CAPACITY", 5: "NC_E_CORRUPT", 6: "NC_E_STATE"}
 NC_FP32, NC_BF16, NC_FP8 = 0, 1, 2
 NC_SKIP_NONE, NC_SKIP_ENTROPY, NC_SKIP_PMAX = 0, 1, 2
-NC_F_HEAD, NC_F_NGRAM, NC_F_SKIP, NC_F_MIXER, NC_F_ENSEMBLE = 1, 2, 4, 8, 16
+NC_F_HEAD, NC_F_NGRAM, NC_F_SKIP, NC_F_MIXER, NC_F_ENSEMBLE, NC_F_EAGER = 1, 2, 4, 8, 16, 32
 NC_MODE_LLM, NC_MODE_SKIP, NC_MODE_MIX, NC_MODE_ENSEMBLE = 0, 1, 2, 3
 
 
@@ -39,7 +39,8 @@ class NcProbe(C.Structure):
 class NcStats(C.Structure):
     _fields_ = [("tokens", C.c_uint64), ("llm_rows", C.c_uint64), ("skipped", C.c_uint64),
                 ("body_rows", C.c_uint64), ("bits", C.c_double), ("ideal_bits", C.c_double),
-                ("seconds", C.c_double), ("wait_seconds", C.c_double)]
+                ("seconds", C.c_double), ("wait_seconds", C.c_double),
+                ("graph_replays", C.c_uint64), ("graph_captures", C.c_uint64)]
 
 
 class NcTile(C.Structure):

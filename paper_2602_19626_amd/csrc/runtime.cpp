@@ -9,6 +9,9 @@
 #include <cstring>
 #include <numeric>
 #include <thread>
+#include <array>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "cdf_dev.hpp"
@@ -153,6 +156,18 @@ struct nc_ctx {
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev_busy;  // (events, class)
   // measured GEMM launch shapes per (GEMM, row bucket); kind T_AUTO = the fixed rule
   GemmTile tiles[NC_G_COUNT][kRowBuckets];
+  // captured transformer passes of the decode / probe paths, by pass shape; every buffer a pass
+  // reads or writes is part of the key, so a reallocation selects (and captures) a new graph
+  struct GraphKey {
+    int n, n_items, n_last;
+    size_t off_rows, off_items, off_last;
+    std::array<const void*, 12> bufs;
+    bool operator<(const GraphKey& o) const {
+      return std::tie(n, n_items, n_last, off_rows, off_items, off_last, bufs) <
+             std::tie(o.n, o.n_items, o.n_last, o.off_rows, o.off_items, o.off_last, o.bufs);
+    }
+  };
+  std::map<GraphKey, hipGraphExec_t> graphs;
 
   ~nc_ctx();
 };
@@ -193,6 +208,7 @@ nc_ctx::~nc_ctx() {
   }
   for (hipEvent_t e : {ev_dist[0], ev_dist[1], ev_pred})
     if (e) (void)hipEventDestroy(e);
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   if (st2) (void)hipStreamDestroy(st2);
   if (st) (void)hipStreamDestroy(st);
 }
@@ -396,7 +412,14 @@ void ensure_step(nc_ctx* c, int B) {
 
 struct BodyOpts {
   bool calib = false;  // FP32 weights with amax recording (FP8 calibration)
+  bool graph = false;  // replay a captured graph of the pass (decode and probe paths)
 };
+
+// Attention of a pass with fewer items runs the parallel quad + fold pair (decode), otherwise one
+// wave per item (prefill); both give the same bits.
+constexpr size_t kAttnParallelItems = 1024;
+// Captured pass shapes kept per context (each a HIP graph of ~180 kernel nodes).
+constexpr size_t kMaxGraphs = 512;
 
 // Small per-step inputs gathered on the host and uploaded with one copy.
 struct Stage {
@@ -614,14 +637,9 @@ GemmArgs args_lm(nc_ctx* c, const void* A, const float* Ainv, const int32_t* a_r
   return a;
 }
 
-// Appends a planned pass to the KV caches; leaves each row's final residual in x, its
-// output-layer operand in yb, and each stream's newest operand row in hlast.  Rows of one stream
-// are consecutive positions spanning fewer than `slide` positions (the ring holds at least
-// ctx_len + slide entries, so no needed key is overwritten).
-void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = {}) {
+// The kernels of one transformer pass (see run_pass).
+void pass_launches(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o) {
   const int n = int(p.rows.size());
-  if (!n) return;
-  ensure_rows(c, n);
   const RowMeta* drows = reinterpret_cast<const RowMeta*>(dstage + p.off_rows);
   const AttnItem* ditems = reinterpret_cast<const AttnItem*>(dstage + p.off_items);
   const int prec = o.calib ? P_F32 : c->prec;
@@ -655,9 +673,8 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
     t.slide = c->cfg.slide;
     t.scale_log2 = float(1.4426950408889634 / std::sqrt((double)c->hd));
     prof_begin(c, NC_K_ATTN);
-    const bool par = p.items.size() < 1024;
+    const bool par = p.items.size() < kAttnParallelItems;
     if (par) {
-      c->aws.alloc(attention_ws_bytes(int(p.items.size())) / 4);
       t.ws = c->aws.p;
       t.ws_bytes = c->aws.n * 4;
     }
@@ -695,7 +712,64 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
                      reinterpret_cast<const uint32_t*>(c->yb.p), c->xinv.p, dl, dl + nl, nl, words,
                      reinterpret_cast<uint32_t*>(c->hlast.p), c->hinv.p);
   NC_HIP(hipGetLastError());
+}
+
+bool profiling(const nc_ctx* c) {
+  for (const auto& P : c->prof)
+    if (P.on) return true;
+  return false;
+}
+
+void graphs_clear(nc_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  c->graphs.clear();
+}
+
+// Appends a planned pass to the KV caches; leaves each row's final residual in x, its
+// output-layer operand in yb, and each stream's newest operand row in hlast.  Rows of one stream
+// are consecutive positions spanning fewer than `slide` positions (the ring holds at least
+// ctx_len + slide entries, so no needed key is overwritten).  With o.graph the pass's ~6 kernels
+// per layer are captured into a HIP graph on the first use of its shape (rows, attention items,
+// stage offsets and buffers) and replayed afterwards: one launch instead of ~180.  A replay runs
+// the same kernels with the same arguments, so the bits are those of the direct launches.
+void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = {}) {
+  const int n = int(p.rows.size());
+  if (!n) return;
+  ensure_rows(c, n);
+  if (p.items.size() < kAttnParallelItems)
+    c->aws.alloc(attention_ws_bytes(int(p.items.size())) / 4);
   c->stats.body_rows += n;
+  if (!o.graph || o.calib || (c->cfg.features & NC_F_EAGER) || profiling(c)) {
+    pass_launches(c, p, dstage, o);
+    return;
+  }
+  nc_ctx::GraphKey k{n,          int(p.items.size()), int(p.last.size()),
+                     p.off_rows, p.off_items,         p.off_last,
+                     {dstage, c->x.p, c->xinv.p, c->xss.p, c->yb.p, c->qb.p, c->ob.p, c->hb.p,
+                      c->aws.p, c->kc.p, c->hlast.p, c->hinv.p}};
+  auto it = c->graphs.find(k);
+  if (it == c->graphs.end()) {
+    if (c->graphs.size() >= kMaxGraphs) graphs_clear(c);
+    hipGraph_t g = nullptr;
+    NC_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    try {
+      pass_launches(c, p, dstage, o);
+    } catch (...) {
+      hipGraph_t tmp = nullptr;
+      (void)hipStreamEndCapture(c->st, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      throw;
+    }
+    NC_HIP(hipStreamEndCapture(c->st, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    NC_HIP(e);
+    it = c->graphs.emplace(k, ex).first;
+    c->stats.graph_captures += 1;
+  }
+  NC_HIP(hipGraphLaunch(it->second, c->st));
+  c->stats.graph_replays += 1;
 }
 
 void run_lm_head(nc_ctx* c, const void* A, const float* Ainv, const int32_t* a_rows, int M,
@@ -745,7 +819,9 @@ void catch_up_now(nc_ctx* c, int s, int upto) {
   Stage st;
   for (auto& p : plans) stage_pass(st, p);
   const uint8_t* d = upload_stage(c, st);
-  for (auto& p : plans) run_pass(c, p, d);
+  BodyOpts o;
+  o.graph = true;
+  for (auto& p : plans) run_pass(c, p, d, o);
   sync(c);
 }
 
@@ -1127,6 +1203,7 @@ nc_status nc_calibrate_fp8(nc_ctx* c, const int32_t* tokens, size_t n) {
     }
     c->sa_lm = sc(am[4 * c->nl]);
     c->fp8_ready = true;
+    graphs_clear(c);  // captured passes carry the activation scales as kernel arguments
     reset_streams(c, 1, int(n) + 1);
   });
 }
@@ -1410,7 +1487,9 @@ nc_status nc_decode_stream(nc_ctx* c, uint32_t ns, const uint8_t* const* in,
         for (auto& p : plans) stage_pass(stg, p);
         const size_t off_tg = stg.put(tg.data(), size_t(B) * 4);
         const uint8_t* dst = upload_stage(c, stg);
-        for (auto& p : plans) run_pass(c, p, dst);
+        BodyOpts o;
+        o.graph = true;
+        for (auto& p : plans) run_pass(c, p, dst, o);
         A.targets = reinterpret_cast<const uint32_t*>(dst + off_tg);
       }
       if (!llm.empty()) {
@@ -1468,6 +1547,7 @@ nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out,
                       uint32_t* n_out) {
   return guard([&] {
     NC_CHECK(c, NC_E_INVALID, "NULL context");
+    graphs_clear(c);  // captured passes carry the launch shapes
     NC_CHECK(max_rows >= 1 && max_rows <= (1u << 20), NC_E_INVALID,
              "max_rows must be in [1, 2^20]");
     NC_CHECK(reps >= 1 && reps <= 1000, NC_E_INVALID, "reps must be in [1, 1000]");
@@ -1582,6 +1662,7 @@ nc_status nc_autotune(nc_ctx* c, uint32_t max_rows, uint32_t reps, nc_tile* out,
 nc_status nc_tiles_set(nc_ctx* c, const nc_tile* t, uint32_t n) {
   return guard([&] {
     NC_CHECK(c && (t || n == 0), NC_E_INVALID, "NULL argument");
+    graphs_clear(c);  // captured passes carry the launch shapes
     static const int kEpi[NC_G_COUNT] = {E_QKV, E_RESID, E_GLU, E_RESID, E_STORE};
     for (uint32_t i = 0; i < n; ++i) {
       const nc_tile& e = t[i];
@@ -1608,6 +1689,7 @@ nc_status nc_tiles_set(nc_ctx* c, const nc_tile* t, uint32_t n) {
 nc_status nc_tiles_reset(nc_ctx* c) {
   return guard([&] {
     NC_CHECK(c, NC_E_INVALID, "NULL context");
+    graphs_clear(c);  // captured passes carry the launch shapes
     for (auto& row : c->tiles)
       for (auto& t : row) t = GemmTile{};
   });

@@ -184,3 +184,10 @@ def test_many_streams_batch_and_alone_agree_bf16(weights):
     dec = ctx.decode_stream(together, [len(s) for s in streams])
     for a, b in zip(dec, streams):
         assert np.array_equal(a, b)
+    st = ctx.stats()
+    assert st["graph_replays"] > st["graph_captures"] > 0
+    eager, _ = make_context(WL, precision="bf16", max_streams=24, graphs=False)
+    assert eager.encode_stream(streams)[0] == together
+    dec_e = eager.decode_stream(together, [len(s) for s in streams])
+    assert all(np.array_equal(a, b) for a, b in zip(dec_e, dec))
+    assert eager.stats()["graph_replays"] == 0

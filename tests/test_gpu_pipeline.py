@@ -175,3 +175,34 @@ def test_nc06_hybrid_round_trip(setup):
     # each text entry's stream is what the pipeline codes for that piece alone
     piece = data[seg[0][1]:seg[0][1] + texts[0].n_bytes]
     assert ctx.encode_stream([nc06.tokens_of(piece)])[0][0] == texts[0].data
+
+
+def test_graph_replayed_passes_match_direct_launches(setup):
+    """Decode passes replayed from captured HIP graphs give the same tokens and the same probe
+    distributions as passes launched kernel by kernel; eager work and synchronisations run between
+    the replays, and every replay's output feeds the next decoded symbol."""
+    _, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    streams = [toks[:900], synth.make_stream(700, WL.shape.vocab, seed=21, span=WL.span),
+               synth.make_stream(333, WL.shape.vocab, seed=22, span=WL.span)]
+    ctxs = {}
+    for graphs in (True, False):
+        cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32",
+                             skip=WL.skip, mix_init=WL.mix_init, max_streams=3, graphs=graphs)
+        ctxs[graphs] = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+    data_g, _ = ctxs[True].encode_stream(streams)
+    data_e, _ = ctxs[False].encode_stream(streams)
+    assert data_g == data_e
+    out = ctxs[True].decode_stream(data_g, [len(s) for s in streams])
+    st = ctxs[True].stats()
+    assert st["graph_captures"] > 0 and st["graph_replays"] > 2 * st["graph_captures"]
+    for a, b in zip(out, streams):
+        assert np.array_equal(a, b)
+    ctxs[False].decode_stream(data_e, [len(s) for s in streams])
+    assert ctxs[False].stats()["graph_replays"] == 0
+    for c in ctxs.values():
+        c.reset(1, 1000)
+    for i in (0, 1, 150, 151, 600, 899):
+        pg = ctxs[True].probs_for_context(0, toks[:i])
+        pe = ctxs[False].probs_for_context(0, toks[:i])
+        assert np.array_equal(pg, pe), i
