@@ -44,6 +44,11 @@ KERNEL_PRIMARY_RE = {"attn": r"attention_(quad|seq)_kernel", "vocab": r"vocab_ls
 PROBE_RE = r"neg"   # the plain streaming probe kernel (torch.neg: reads N bytes, writes N bytes)
 
 
+def log(msg: str):
+    """Progress on stderr (the JSON line on stdout stays the only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash(kernel: str) -> str:
     p = os.path.join(ROOT, "paper_2602_19626_amd", "csrc", KERNEL_SOURCES[kernel])
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
@@ -265,6 +270,65 @@ def batched_line(nc, synth, max_len: int, steps: int = 1):
             "roundtrip_exact": bool(ok)}
 
 
+def precision_lines(nc, synth, wl, weights, stream, n: int, ref=None):
+    """The precision forms on the plain configuration's stream prefix (the KV cache slides at
+    token 2,048): max |logit error| and mean KL(p_llm) against the FP64 oracle at sampled
+    positions (skip off, so the model runs there), and the coded length against the oracle
+    coder's on the same prefix (method as specified).  Tolerances: the error model of
+    tests/golden/precision_tolerances.json."""
+    import dataclasses
+    from oracle.transformer import Transformer
+    toks = stream[:n]
+    pos = [p for p in (0, 100, 500, 1000, 1500, 2046, 2047, 2048, 2049, 2100, n - 1) if p < n]
+    model = Transformer(wl.shape, weights, max_block=512)
+    x = np.concatenate([[0], toks[:-1]])
+    z_ref = model.logits(model.append(x)[pos])
+    tol = json.load(open(os.path.join(ROOT, "tests", "golden", "precision_tolerances.json")))
+    calib = synth.make_stream(2048, wl.shape.vocab, synth.CALIBRATION_SEED, span=wl.span)
+    out = {}
+    for prec in ("fp32", "bf16", "fp8"):
+        row = {}
+        for skip in ("none", wl.skip):
+            w2 = dataclasses.replace(wl, precision=prec, skip=skip)
+            cfg = nc.make_config(w2.shape, ngram_order=w2.ngram_order, precision=prec, skip=skip,
+                                 mix_init=w2.mix_init, warmup=w2.warmup, head_lr=w2.head_lr,
+                                 cdf_total=w2.cdf_total, max_streams=1)
+            ctx = nc.Context(cfg, synth.flat_weights(w2.shape, weights))
+            if prec == "fp8":
+                ctx.calibrate_fp8(calib)
+            if skip == "none":
+                ctx.reset(1, n + 1)
+                errs, kls = [], []
+                for k, i in enumerate(pos):
+                    _, pr = ctx.probs_for_context(0, toks[:i], probe=True)
+                    z = pr["logits"].astype(np.float64)
+                    errs.append(float(np.max(np.abs(z - z_ref[k]))))
+                    zr = z_ref[k] - z_ref[k].max()
+                    pref = np.exp(zr) / np.exp(zr).sum()
+                    q = np.exp(z - z.max())
+                    q /= q.sum()
+                    kls.append(float(np.sum(pref * (np.log2(pref) - np.log2(q)))))
+                row.update(max_abs_logit_err=round(max(errs), 6), mean_kl_llm_bits=float(
+                    f"{np.mean(kls):.4g}"), positions=pos)
+                if prec != "fp32":
+                    row["tolerance"] = {"max_abs_logit": round(tol[prec]["max_abs_logit"], 4),
+                                        "mean_kl_bits": float(f"{tol[prec]['mean_kl_bits']:.4g}")}
+            else:
+                _, bits = ctx.encode_stream([toks])
+                row["coded_bits"] = int(bits[0])
+                if ref is not None:
+                    row["oracle_coded_bits"] = int(ref.n_bits)
+                    row["gap_vs_oracle_coder_bits_per_token"] = round(
+                        (bits[0] - ref.n_bits) / n, 5)
+                    row["gap_vs_oracle_ideal_bits_per_token"] = round(
+                        (bits[0] - ref.ideal_bits) / n, 5)
+                    row["gap_vs_oracle_ideal_bpb_at_4_bytes_per_token"] = round(
+                        (bits[0] - ref.ideal_bits) / n / 4.0, 5)
+            ctx.close()
+        out[prec] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +344,8 @@ def main():
     ap.add_argument("--cpu-single-sample", type=int, default=256,
                     help="oracle prefix timed with one BLAS thread (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16 / FP8 lines (logit error, KL, coded length vs oracle)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain streaming kernel of this size first (counter scaling)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -344,6 +410,7 @@ def main():
         # segment at once; timed outside the measured steps
         t0 = time.perf_counter()
         table = ctx.autotune(max_rows=len(streams) * wl.shape.slide, reps=5)
+        log("launch shapes tuned")
         tune = {"seconds": round(time.perf_counter() - t0, 3), "entries": len(table),
                 "changed": sum(e["kind"] != "rule" for e in table),
                 "est_saving_us": round(sum(e["us_default"] - e["us_best"] for e in table), 1)}
@@ -360,12 +427,14 @@ def main():
         st_dec = ctx.stats()
         return data, bits, out, te - t0, td - te, st_enc, st_dec
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         step()
+        log(f"warmup step {k + 1}/{args.warmup} done")
     t_enc = t_dec = w_enc = w_dec = 0.0
     ok = True
-    for _ in range(args.steps):
+    for k in range(args.steps):
         data, bits, out, te, td, st_enc, st_dec = step()
+        log(f"timed step {k + 1}/{args.steps}: encode {te:.2f} s, decode {td:.2f} s")
         t_enc += te
         t_dec += td
         w_enc += st_enc["wait_seconds"]
@@ -381,6 +450,7 @@ def main():
     from paper_2602_19626_amd._lib import KERNEL_CLASSES
     prof = {k: ctx.profile_read(k) for k in KERNEL_CLASSES}
     ctx.profile(None)
+    log("profiled step done")
     classes = class_rooflines(prof, wl.precision)
     kern = args.kernel if args.kernel != "auto" else \
         max(classes, key=lambda k: classes[k]["est_total_ms"])
@@ -410,16 +480,21 @@ def main():
             "host_wait_frac": {"encode": round(w_enc / t_enc, 3), "decode": round(w_dec / t_dec, 3)},
             "roofline": roofline, "kernel_classes": classes, "autotune": tune}
     line["cdf24_standalone"] = cdf24_standalone(nc, torch, wl.shape.vocab)
+    log("CDF-24 standalone timed")
     line["gpu_ideal_bits_per_token"] = round(ideal_enc / n_tok, 5)
     if args.batch_len and args.workload == "full_fp32":
         b = batched_line(nc, synth, args.batch_len)
+        log("64-stream BF16 line done")
         b["vs_this_line_value"] = round(b["value"] / line["value"], 2)
         line["batch64_bf16"] = b
 
     if not args.no_cpu_baseline:
         n_s = min(args.cpu_sample, len(streams[0]))
+        log(f"oracle baseline on {n_s} tokens (all threads) and "
+            f"{min(args.cpu_single_sample, len(streams[0]))} tokens (one thread) ...")
         ref, cb = cpu_baseline(wl, weights, streams[0], n_s,
                                min(args.cpu_single_sample, len(streams[0])))
+        log("oracle baseline done")
         line["cpu_baseline"] = cb
         # gap of the GPU coder against the oracle's ideal code length, same prefix
         d, b = ctx.encode_stream([streams[0][:n_s]])
@@ -430,6 +505,10 @@ def main():
         # against the oracle's own coder on its quantised CDFs, and its quantised ideal length
         line["coded_bits_sample"] = {"gpu": int(b[0]), "oracle": int(ref.n_bits),
                                      "oracle_quantised_ideal": round(ref.quant_bits, 3)}
+        if args.workload == "full_fp32" and not args.no_precision:
+            log("precision forms against the oracle ...")
+            line["precision_forms"] = precision_lines(nc, synth, wl, weights, streams[0], n_s, ref)
+            log("precision forms done")
     print(json.dumps(line), flush=True)
 
 
