@@ -102,6 +102,77 @@ def traffic_from(fetch_csv: str, write_csv: str, kernel: str, workload: str, pro
     return t
 
 
+def stats_summary(stats_csv: str, title: str, command: str, top: int = 24) -> str:
+    """Markdown table of the top kernels of a rocprofv3 --stats kernel_stats.csv."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    calls = sum(int(r["Calls"]) for r in rows)
+    out = [f"# {title}", "", "Command (from the repository root, on one MI355X):", "", "```",
+           command, "```", "", "| kernel | calls | total ms | avg us | % |",
+           "|---|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        name = r["Name"].replace("|", "/")
+        name = name if len(name) <= 90 else name[:87] + "..."
+        out.append(f"| `{name}` | {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / tot:.2f} |")
+    out += ["", f"Total kernel time {tot / 1e6:.1f} ms over {calls} launches", ""]
+    return "\n".join(out)
+
+
+def pmc_summary(paths, title: str, command: str, probe_mib: int = 0, simds: int = 1024,
+                top: int = 30) -> str:
+    """Per-kernel sums of rocprofv3 --pmc counter files: dispatches, counter totals, and the
+    derived figures when their counters are present (MFMA busy share of the SIMD cycles; HBM
+    bytes per dispatch from FETCH_SIZE / WRITE_SIZE, each scaled by the same counter's reading
+    for the streaming probe of probe_mib MiB)."""
+    per = {}
+    for path in paths:
+        for row in csv.DictReader(open(path)):
+            k = per.setdefault(row["Kernel_Name"], {"ids": set()})
+            k["ids"].add(row.get("Dispatch_Id", row.get("Correlation_Id", "")))
+            c = row["Counter_Name"]
+            k[c] = k.get(c, 0.0) + float(row["Counter_Value"])
+            k["n_" + c] = k.get("n_" + c, 0) + 1
+    scale = {}
+    if probe_mib:
+        for name, k in per.items():
+            if re.search(PROBE_RE, name):
+                for c in ("FETCH_SIZE", "WRITE_SIZE"):
+                    if c in k:
+                        scale[c] = probe_mib * 1024.0 / k[c]
+    out = [f"# {title}", "", "Commands (from the repository root, on one MI355X):", "", "```",
+           command, "```", ""]
+    counters = sorted({c for k in per.values() for c in k if c != "ids" and not c.startswith("n_")})
+    out.append("Counters: " + ", ".join(counters) + (f"; FETCH/WRITE scale from the probe: "
+               + ", ".join(f"{c} x{v:.4f}" for c, v in scale.items()) if scale else ""))
+    out.append("")
+    hdr = "| kernel | dispatches |"
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in counters and "GRBM_GUI_ACTIVE" in counters:
+        hdr += " MFMA busy % |"
+    if "MfmaUtil" in counters:
+        hdr += " MfmaUtil % (mean) |"
+    if "FETCH_SIZE" in counters:
+        hdr += " fetch KB / dispatch |"
+    if "WRITE_SIZE" in counters:
+        hdr += " write KB / dispatch |"
+    out += [hdr, "|---|---:|" + "---:|" * (hdr.count("|") - 3)]
+    key = next((c for c in ("GRBM_GUI_ACTIVE", "FETCH_SIZE") if c in counters), counters[0])
+    for name, k in sorted(per.items(), key=lambda kv: -kv[1].get(key, 0.0))[:top]:
+        n = max(len(k["ids"]), 1)
+        nm = name if len(name) <= 80 else name[:77] + "..."
+        line = f"| `{nm}` | {n} |"
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in counters and "GRBM_GUI_ACTIVE" in counters:
+            line += f" {100 * k.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) / max(k['GRBM_GUI_ACTIVE'] * simds, 1):.1f} |"
+        if "MfmaUtil" in counters:
+            line += f" {k.get('MfmaUtil', 0) / max(k.get('n_MfmaUtil', 1), 1):.1f} |"
+        if "FETCH_SIZE" in counters:
+            line += f" {k.get('FETCH_SIZE', 0) * scale.get('FETCH_SIZE', 1.0) / n:.1f} |"
+        if "WRITE_SIZE" in counters:
+            line += f" {k.get('WRITE_SIZE', 0) * scale.get('WRITE_SIZE', 1.0) / n:.1f} |"
+        out.append(line)
+    return "\n".join(out) + "\n"
+
+
 def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024, 4096), reps: int = 20):
     """nc_quantize_cdf24 alone on float32 rows of softmax-shaped probabilities (up to 64 rows the
     segment reduce + scan kernels, more rows the one-workgroup-per-row kernel); algorithmic bytes
@@ -351,6 +422,11 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="offline: turn two rocprofv3 --pmc counter files into the traffic figure")
     ap.add_argument("--traffic-command", default="", help="the counter runs' command, recorded")
+    ap.add_argument("--stats-summary", nargs=3, metavar=("STATS_CSV", "TITLE", "OUT_MD"),
+                    help="offline: markdown summary of a rocprofv3 --stats kernel_stats.csv")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="ARG",
+                    help="offline: TITLE OUT_MD CSV [CSV ...]: per-kernel counter summary")
+    ap.add_argument("--summary-command", default="", help="the profiled command, recorded")
     ap.add_argument("--ablation", action="store_true",
                     help="run the A0-A4 feature ladder on the workload instead of the timing")
     ap.add_argument("--oracle-prefix", type=int, default=200)
@@ -366,6 +442,15 @@ def main():
     if args.traffic_from:
         print(json.dumps(traffic_from(*args.traffic_from, args.kernel, args.workload,
                                       args.copy_probe_mib, args.traffic_command)))
+        return
+    if args.stats_summary:
+        csv_path, title, out_md = args.stats_summary
+        open(out_md, "w").write(stats_summary(csv_path, title, args.summary_command))
+        return
+    if args.pmc_summary:
+        title, out_md, *paths = args.pmc_summary
+        open(out_md, "w").write(pmc_summary(paths, title, args.summary_command,
+                                            args.copy_probe_mib))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (streams are "
