@@ -1448,13 +1448,18 @@ __global__ __launch_bounds__(256) void attention_seq_kernel(const AttnArgs a) {
 }
 
 // Few items (decode), first kernel: one 4-wave workgroup per (item, quad); wave w computes chunk
-// 4 Q + w, wave 0 folds the quad in order and stores its state.
+// 4 Q + w, wave 0 folds the quad in order and stores its state.  Work unit u = item + n_items * qi
+// is placed by an XCD-aware bijection of the 1-D grid (dispatch is round-robin over the 8 XCDs):
+// XCD x runs a contiguous range of units, so the items of one stream and kv head (consecutive in
+// the item list: the column blocks of a multi-row pass) read the same K/V chunk from one L2.
 template <int PA>
 __global__ __launch_bounds__(256) void attention_quad_kernel(const AttnArgs a) {
   __shared__ float part[QCH][QSTATE * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int item = blockIdx.x, qi = blockIdx.y;
+  const int nu = gridDim.x, q8 = nu / 8, r8 = nu % 8, xcd = blockIdx.x % 8;
+  const int u = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
+  const int item = u % a.n_items, qi = u / a.n_items;
   const AttnItem it = a.items[item];
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);
@@ -1744,7 +1749,7 @@ template <int PA, int PO>
 static void attn_go(const AttnArgs& a, bool parallel, hipStream_t s) {
   if (parallel) {
     const int nq = attention_quads(a.ctx_len);
-    hipLaunchKernelGGL((attention_quad_kernel<PA>), dim3(a.n_items, nq), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((attention_quad_kernel<PA>), dim3(a.n_items * nq), dim3(256), 0, s, a);
     hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64 * FOLD_WAVES), 0, s,
                        a);
   } else {
