@@ -505,9 +505,11 @@ def main():
         t0 = time.perf_counter()
         data, bits = ctx.encode_stream(streams)
         te = time.perf_counter()
+        log(f"  encode {te - t0:.2f} s")
         st_enc = ctx.stats()
         out = ctx.decode_stream(data, [len(s) for s in streams])
         td = time.perf_counter()
+        log(f"  decode {td - te:.2f} s")
         torch.cuda.synchronize()
         st_dec = ctx.stats()
         return data, bits, out, te - t0, td - te, st_enc, st_dec

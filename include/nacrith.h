@@ -94,8 +94,9 @@ typedef struct nc_probe {
 /* Per-call statistics of the last encode/decode on a context. */
 typedef struct nc_stats {
   uint64_t tokens;           /* tokens coded */
-  uint64_t llm_rows;         /* positions whose logits were used (not skipped) */
-  uint64_t skipped;          /* positions coded by the n-gram alone */
+  uint64_t llm_rows;         /* decode: positions whose logits were used (not skipped) */
+  uint64_t skipped;          /* decode: positions coded by the n-gram alone (encode: 0; its
+                                modes are decided on the device) */
   uint64_t body_rows;        /* transformer rows evaluated (KV appends) */
   double bits;               /* exact coded bits (sum over streams) */
   double ideal_bits;         /* sum -log2 p_i(t_i) of the float32 coding distributions */

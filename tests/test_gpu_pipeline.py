@@ -206,3 +206,33 @@ def test_graph_replayed_passes_match_direct_launches(setup):
         pg = ctxs[True].probs_for_context(0, toks[:i])
         pe = ctxs[False].probs_for_context(0, toks[:i])
         assert np.array_equal(pg, pe), i
+
+
+def test_edge_cases_empty_single_and_degenerate_streams(setup):
+    """Empty and one-token streams beside ordinary ones, a constant stream (the n-gram becomes
+    certain, so most positions skip the model), a stream of the largest token id, and a stream
+    whose length puts a slide exactly at its last position: exact round trips, batch-invariant
+    bytes, and the coded length of the constant stream within 0.01 bits/token of the oracle."""
+    _, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    L = WL.shape.ctx_len
+    streams = [np.zeros(0, np.int32), np.array([7], np.int32), np.full(400, 3, np.int32),
+               np.full(50, WL.shape.vocab - 1, np.int32), toks[:L + 1], toks[:L + WL.shape.slide]]
+    cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32", skip=WL.skip,
+                         mix_init=WL.mix_init, max_streams=len(streams))
+    ctx = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+    data, bits = ctx.encode_stream(streams)
+    assert ctx.stats()["tokens"] == sum(len(s) for s in streams)
+    assert bits[0] >= 0 and len(data[0]) <= nc.encode_bound(0)
+    out = ctx.decode_stream(data, [len(s) for s in streams])
+    for a, b in zip(out, streams):
+        assert np.array_equal(a, b)
+    for k in (1, 2, 5):
+        assert ctx.encode_stream([streams[k]])[0][0] == data[k], k
+    ref = op.encode(op.Settings.from_workload(WL), WL.shape, w, streams[2], block=1,
+                    quantize=False)
+    assert abs(bits[2] - ref.ideal_bits) / len(streams[2]) < 0.01 + 9.0 / len(streams[2])
+    ctx.decode_stream([data[2]], [len(streams[2])])
+    assert ctx.stats()["skipped"] > 250              # the constant stream mostly skips
+    with pytest.raises(nc.NacrithError):            # more streams than the context holds
+        ctx.encode_stream(streams + [streams[1]])
