@@ -1288,6 +1288,7 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
             Vt + sbase + (long long)(hc * 16 + col) * a.ring + vslot + 8 * h);
         vf[hb][h] = hb < nhb ? v : v4i{0, 0, 0, 0};
       }
+    __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first MFMA
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       st[b] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1337,6 +1338,9 @@ __device__ __forceinline__ ChunkState chunk_partial(const AttnArgs& a, const Att
             Vt + sbase + (long long)(hc * 16 + col) * a.ring + vslot + 4 * b);
         vf[hb][b] = hb < nhb ? v : v4f{0.f, 0.f, 0.f, 0.f};
       }
+    // every load above is issued before the first MFMA (the scheduler would otherwise sink the
+    // V^T loads behind the score chains, adding a memory round trip)
+    __builtin_amdgcn_sched_barrier(0);
     // the four blocks' MFMA chains interleaved step by step
 #pragma unroll
     for (int b = 0; b < 4; ++b) st[b] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1448,18 +1452,25 @@ __global__ __launch_bounds__(256) void attention_seq_kernel(const AttnArgs a) {
 }
 
 // Few items (decode), first kernel: one 4-wave workgroup per (item, quad); wave w computes chunk
-// 4 Q + w, wave 0 folds the quad in order and stores its state.  Work unit u = item + n_items * qi
-// is placed by an XCD-aware bijection of the 1-D grid (dispatch is round-robin over the 8 XCDs):
-// XCD x runs a contiguous range of units, so the items of one stream and kv head (consecutive in
-// the item list: the column blocks of a multi-row pass) read the same K/V chunk from one L2.
+// 4 Q + w, wave 0 folds the quad in order and stores its state.  When several items share a
+// stream's K/V (the column blocks of a multi-row pass, consecutive in the item list), work unit
+// u = item + n_items * qi is placed by an XCD-aware bijection of the 1-D grid (dispatch is
+// round-robin over the 8 XCDs): XCD x runs a contiguous range of units, so those items read the
+// same K/V chunks from one L2.  Otherwise (one row per stream, where contiguous ranges would
+// gather the empty units past short windows on a few XCDs) the units keep the round-robin order.
 template <int PA>
 __global__ __launch_bounds__(256) void attention_quad_kernel(const AttnArgs a) {
   __shared__ float part[QCH][QSTATE * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int nu = gridDim.x, q8 = nu / 8, r8 = nu % 8, xcd = blockIdx.x % 8;
-  const int u = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
-  const int item = u % a.n_items, qi = u / a.n_items;
+  const int nu = gridDim.x;
+  int item = blockIdx.x % a.n_items, qi = blockIdx.x / a.n_items;
+  if (a.xcd_place) {
+    const int q8 = nu / 8, r8 = nu % 8, xcd = blockIdx.x % 8;
+    const int u = xcd * q8 + min(xcd, r8) + blockIdx.x / 8;
+    item = u % a.n_items;
+    qi = u / a.n_items;
+  }
   const AttnItem it = a.items[item];
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);

@@ -83,6 +83,7 @@ struct AttnArgs {
   float scale_log2;     // log2(e) / sqrt(hd)
   float* ws;            // group states of the parallel path
   size_t ws_bytes;
+  int xcd_place;        // parallel path: items share a stream's K/V; place them XCD-aware
 };
 
 // Launch shape of one GEMM.  Every shape evaluates the same per-part MFMA chains and adds them in

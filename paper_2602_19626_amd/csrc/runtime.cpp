@@ -439,6 +439,7 @@ struct PassPlan {
   std::vector<AttnItem> items;
   std::vector<int32_t> last;  // n_last source rows, then n_last destination streams
   double attn_bytes = 0, attn_flops = 0;
+  bool shared_kv = false;     // some stream's kv head has several attention items
   size_t off_rows = 0, off_items = 0, off_last = 0;
 };
 
@@ -458,6 +459,7 @@ PassPlan plan_pass(nc_ctx* c, std::vector<RowMeta> rows, bool calib = false) {
     int j = i;
     while (j + 1 < n && R[j + 1].stream == R[i].stream && R[j + 1].pos == R[j].pos + 1) ++j;
     const int nq = j - i + 1;
+    if (nq * g > 16) p.shared_kv = true;
     for (int kvh = 0; kvh < c->hk; ++kvh)
       for (int c0 = 0; c0 < nq * g; c0 += 16) {
         AttnItem it{};
@@ -672,6 +674,7 @@ void pass_launches(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts
     t.ctx_len = c->cfg.ctx_len;
     t.slide = c->cfg.slide;
     t.scale_log2 = float(1.4426950408889634 / std::sqrt((double)c->hd));
+    t.xcd_place = p.shared_kv ? 1 : 0;
     prof_begin(c, NC_K_ATTN);
     const bool par = p.items.size() < kAttnParallelItems;
     if (par) {
