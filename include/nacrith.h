@@ -48,8 +48,12 @@ enum {
   NC_F_SKIP = 1u << 2,      /* confidence-based LLM skip, section 3.8 */
   NC_F_MIXER = 1u << 3,     /* linear context mixer, section 3.6 */
   NC_F_ENSEMBLE = 1u << 4,  /* softmax-gated {LLM, n-gram orders 1..K} head trained by SGD */
-  NC_F_EAGER = 1u << 5      /* launch every kernel of a decode / probe transformer pass directly
-                               instead of replaying a captured HIP graph of the pass (same bits) */
+  NC_F_EAGER = 1u << 5,     /* launch every kernel directly: no captured HIP graph is replayed
+                               (the batched encode replays captured chunks of its per-position
+                               steps otherwise; same bits either way) */
+  NC_F_DECODE_GRAPHS = 1u << 6  /* also replay captured HIP graphs of the decode / probe
+                                   transformer passes (same bits; measured about 1.5% slower
+                                   than direct launches, so off by default) */
 };
 enum { NC_MODE_LLM = 0, NC_MODE_SKIP = 1, NC_MODE_MIX = 2, NC_MODE_ENSEMBLE = 3 };
 

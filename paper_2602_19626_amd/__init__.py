@@ -11,8 +11,8 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (NC_BF16, NC_F_EAGER, NC_F_ENSEMBLE, NC_F_HEAD, NC_F_MIXER, NC_F_NGRAM,
-                   NC_F_SKIP, NC_FP8,
+from ._lib import (NC_BF16, NC_F_DECODE_GRAPHS, NC_F_EAGER, NC_F_ENSEMBLE, NC_F_HEAD,
+                   NC_F_MIXER, NC_F_NGRAM, NC_F_SKIP, NC_FP8,
                    NC_FP32, NC_SKIP_ENTROPY, NC_SKIP_NONE, NC_SKIP_PMAX, NacrithError, NcConfig,
                    NcProbe, NcStats, check, lib)
 
@@ -107,12 +107,13 @@ def make_config(shape, *, ngram_order=4, precision="fp32", skip="entropy", mix_i
                 warmup=100, head_lr=1e-3, cdf_total=1 << 24, max_streams=1, use_head=True,
                 use_ngram=True, use_skip=True, use_mixer=True, ensemble=False,
                 ngram_eps=5.0, ngram_max_contexts=500_000, mix_eta=1.0,
-                skip_entropy_bits=1.5, skip_pmax=0.99, graphs=True) -> NcConfig:
+                skip_entropy_bits=1.5, skip_pmax=0.99, graphs=True,
+                decode_graphs=False) -> NcConfig:
     """nc_config from a model shape (any object with the ModelShape fields) and options."""
     feats = ((NC_F_HEAD if use_head else 0) | (NC_F_NGRAM if use_ngram else 0)
              | (NC_F_SKIP if (use_skip and skip != "none") else 0)
              | (NC_F_MIXER if use_mixer else 0) | (NC_F_ENSEMBLE if ensemble else 0)
-             | (0 if graphs else NC_F_EAGER))
+             | (0 if graphs else NC_F_EAGER) | (NC_F_DECODE_GRAPHS if decode_graphs else 0))
     return NcConfig(n_layers=shape.n_layers, d_model=shape.d_model, n_heads=shape.n_heads,
                     n_kv_heads=shape.n_kv_heads, head_dim=shape.head_dim, d_ffn=shape.d_ffn,
                     vocab=shape.vocab, rope_theta=shape.rope_theta, norm_eps=shape.norm_eps,

@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "NC_OK", 1: "NC_E_INVALID", 2: "NC_E_DEVICE", 3: "NC_E_NOMEM"
 NC_FP32, NC_BF16, NC_FP8 = 0, 1, 2
 NC_SKIP_NONE, NC_SKIP_ENTROPY, NC_SKIP_PMAX = 0, 1, 2
 NC_F_HEAD, NC_F_NGRAM, NC_F_SKIP, NC_F_MIXER, NC_F_ENSEMBLE, NC_F_EAGER = 1, 2, 4, 8, 16, 32
+NC_F_DECODE_GRAPHS = 64
 NC_MODE_LLM, NC_MODE_SKIP, NC_MODE_MIX, NC_MODE_ENSEMBLE = 0, 1, 2, 3
 
 

@@ -297,7 +297,8 @@ __device__ __forceinline__ void v3_seg(const VocabParams& P, const StreamState& 
     row_fetch(P, S, A, r, s, seg, tid, v);
     R = make_row(P, S, A, r, s, nseg);
   }
-  const int i_pos = !active ? 0 : (A.pos >= 0 ? A.pos : S.ncommit[s]);
+  const int i_pos = !active ? 0 : (A.pos >= 0 ? A.pos + (A.pos_base ? *A.pos_base : 0)
+                                               : S.ncommit[s]);
   const uint32_t key =
       !active ? 0u
               : (A.decode ? (A.targets ? A.targets[r] : A.targets_in[r])
@@ -499,7 +500,7 @@ __device__ __forceinline__ void v5_row(const VocabParams& P, const StreamState& 
   const bool given = A.pos >= 0 && !A.decode;
   const bool counts = (A.upd & kUpdCounts) != 0, mixer = (A.upd & kUpdMixer) != 0;
   const Outcome o = (mixer || !given) ? A.out[r] : Outcome{};
-  const int i = k < 0 ? 0 : (A.pos >= 0 ? A.pos : S.ncommit[s]);
+  const int i = k < 0 ? 0 : (A.pos >= 0 ? A.pos + (A.pos_base ? *A.pos_base : 0) : S.ncommit[s]);
   const int sym = given ? hist[i] : o.sym;
   const bool on = k >= 0 && sym >= 0 && (given || o.sym >= 0);
   __syncthreads();
@@ -729,7 +730,8 @@ __device__ __forceinline__ int slot_last(const FixLds& F, int q, int ln, int tok
 __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& S,
                                        const int32_t* rows, const NgPart* parts, int nseg,
                                        StepOut* step_out, const Outcome* out, int r, int tid,
-                                       bool active, FixLds& F, int pos_given) {
+                                       bool active, FixLds& F, int pos_given,
+                                       const int* pos_base) {
   const int nt = kSegThreads;
   const int V = P.V;
   const int s = rows[r];
@@ -741,7 +743,7 @@ __device__ __forceinline__ void v7_row(const VocabParams& P, const StreamState& 
   uint32_t pre_cl = 0, pre_ch = 0;
   float pre_p = 0.f;
   if (active && tid == 0) {
-    pre_pos = pos_given >= 0 ? pos_given : S.ncommit[s];
+    pre_pos = pos_given >= 0 ? pos_given + (pos_base ? *pos_base : 0) : S.ncommit[s];
     if (step_out) {
       pre_sym = out[r].sym;
       pre_cl = out[r].cl;
@@ -901,9 +903,11 @@ __global__ __launch_bounds__(kSegThreads) void ngram_fix_kernel(VocabParams P, S
                                                                 const int32_t* rows,
                                                                 const NgPart* parts, int nseg,
                                                                 StepOut* step_out,
-                                                                const Outcome* out, int pos) {
+                                                                const Outcome* out, int pos,
+                                                                const int* pos_base) {
   __shared__ FixLds F;
-  v7_row(P, S, rows, parts, nseg, step_out, out, blockIdx.x, threadIdx.x, true, F, pos);
+  v7_row(P, S, rows, parts, nseg, step_out, out, blockIdx.x, threadIdx.x, true, F, pos,
+         pos_base);
 }
 
 // ---- reset -----------------------------------------------------------------------------------
@@ -1133,13 +1137,22 @@ void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArg
 
 void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
                           NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s,
-                          int pos) {
+                          int pos, const int* pos_base) {
   if (B <= 0) return;
   const int nseg = int(ceil_div(P.V, kSeg));
   hipLaunchKernelGGL(ngram_dense_kernel, dim3(nseg, B), dim3(kSegThreads), 0, s, P, S, rows,
                      parts);
   hipLaunchKernelGGL(ngram_fix_kernel, dim3(B), dim3(256), 0, s, P, S, rows, parts, nseg,
-                     step_out, out, pos);
+                     step_out, out, pos, pos_base);
+  NC_HIP(hipGetLastError());
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+void launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, p, v);
   NC_HIP(hipGetLastError());
 }
 

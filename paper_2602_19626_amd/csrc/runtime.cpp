@@ -168,6 +168,10 @@ struct nc_ctx {
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // captured chunks of the batched encode's per-position steps, by (positions, active rows, the
+  // state buffers' addresses); a replay reads its first position from posbase
+  std::map<std::vector<const void*>, hipGraphExec_t> egraphs;
+  DevBuf<int32_t> posbase;
 
   ~nc_ctx();
 };
@@ -209,6 +213,7 @@ nc_ctx::~nc_ctx() {
   for (hipEvent_t e : {ev_dist[0], ev_dist[1], ev_pred})
     if (e) (void)hipEventDestroy(e);
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : egraphs) (void)hipGraphExecDestroy(g.second);
   if (st2) (void)hipStreamDestroy(st2);
   if (st) (void)hipStreamDestroy(st);
 }
@@ -726,6 +731,8 @@ bool profiling(const nc_ctx* c) {
 void graphs_clear(nc_ctx* c) {
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
   c->graphs.clear();
+  for (auto& g : c->egraphs) (void)hipGraphExecDestroy(g.second);
+  c->egraphs.clear();
 }
 
 // Appends a planned pass to the KV caches; leaves each row's final residual in x, its
@@ -742,7 +749,8 @@ void run_pass(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o = 
   if (p.items.size() < kAttnParallelItems)
     c->aws.alloc(attention_ws_bytes(int(p.items.size())) / 4);
   c->stats.body_rows += n;
-  if (!o.graph || o.calib || (c->cfg.features & NC_F_EAGER) || profiling(c)) {
+  if (!o.graph || o.calib || (c->cfg.features & NC_F_EAGER) ||
+      !(c->cfg.features & NC_F_DECODE_GRAPHS) || profiling(c)) {
     pass_launches(c, p, dstage, o);
     return;
   }
@@ -981,25 +989,89 @@ void vocab_commit_step(nc_ctx* c, const StepArgs& A) {
 // st waits for the prediction of pos (ev_pred); st2 waits for the distribution of pos - 1
 // (ev_dist of its parity; at pos 0 for everything st has queued).  Every kernel computes what the
 // sequential step computes, so the coded bytes are the same.
-void encode_step_pipelined(nc_ctx* c, StepArgs A, int pos) {
+// kpos >= 0: the kernels see position kpos + *A.pos_base (a step captured into a graph); the
+// first step of a capture forks st2 from st inside the capture, and its predecessors are complete
+// before the graph starts.
+void encode_step_pipelined(nc_ctx* c, StepArgs A, int pos, int kpos = -1,
+                           bool capture_first = false) {
   const double V = c->V;
   const int par = pos & 1;
   const StreamState Sp = state_par(c, par), Sn = state_par(c, par ^ 1);
-  A.pos = pos;
-  if (pos > 0) NC_HIP(hipStreamWaitEvent(c->st, c->ev_pred, 0));
+  A.pos = kpos >= 0 ? kpos : pos;
+  if (pos > 0 && !capture_first) NC_HIP(hipStreamWaitEvent(c->st, c->ev_pred, 0));
   prof_begin(c, NC_K_VOCAB);
   launch_vocab_dist(c->vp, Sp, A, c->st);
   A.upd = kUpdMixer;
   launch_ngram_update(c->vp, Sp, A, c->st);
   prof_end(c, NC_K_VOCAB, A.B * V * 4.0 * (2 + 2 + 2 + 2 + 1), A.B * V * 12.0);
   NC_HIP(hipEventRecord(c->ev_dist[par], c->st));
-  NC_HIP(hipStreamWaitEvent(c->st2, c->ev_dist[pos > 0 ? par ^ 1 : par], 0));
+  NC_HIP(hipStreamWaitEvent(c->st2, c->ev_dist[(pos > 0 && !capture_first) ? par ^ 1 : par], 0));
   A.upd = kUpdCounts;
   launch_ngram_update(c->vp, Sn, A, c->st2);
   prof_begin(c, NC_K_NGRAM, c->st2);
-  launch_ngram_predict(c->vp, Sn, A.rows, A.B, c->ngp.p, nullptr, nullptr, c->st2, pos + 1);
+  launch_ngram_predict(c->vp, Sn, A.rows, A.B, c->ngp.p, nullptr, nullptr, c->st2, A.pos + 1,
+                       A.pos_base);
   prof_end(c, NC_K_NGRAM, A.B * V * 4.0 * 2, A.B * V * 8.0, c->st2);
   NC_HIP(hipEventRecord(c->ev_pred, c->st2));
+}
+
+// Positions p0 .. p0 + np - 1 of the pipelined encode (B rows each, logits in zseg rows
+// (i - p0) * B), captured on the first use of the shape and replayed afterwards: one launch
+// instead of about ten launches and event calls per position.  p0 is even, so the parity
+// buffers alternate as in the direct path; the kernels compute exactly what they compute there.
+void encode_chunk_graph(nc_ctx* c, int p0, int np, int B) {
+  c->posbase.alloc(1);
+  const StreamState S = c->S;
+  std::vector<const void*> key{reinterpret_cast<const void*>(size_t(np)),
+                               reinterpret_cast<const void*>(size_t(B)),
+                               reinterpret_cast<const void*>(size_t(c->n_streams)),
+                               c->zseg.p, c->iv.p, c->ptok.p, c->steprows.p, c->lsep.p, c->segp.p,
+                               c->ngp.p, c->outc.p, c->posbase.p, S.b, S.png, S.uni, S.hist,
+                               S.pool, S.keys, S.lw, S.mode,
+                               reinterpret_cast<const void*>(size_t(c->S_alloc)),
+                               reinterpret_cast<const void*>(size_t(c->T_alloc)),
+                               reinterpret_cast<const void*>(size_t(S.cap)),
+                               reinterpret_cast<const void*>(size_t(S.maxctx))};
+  // everything queued before the chunk, on both streams, precedes the replay
+  NC_HIP(hipStreamWaitEvent(c->st, c->ev_pred, 0));
+  launch_set_int(c->posbase.p, p0, c->st);
+  auto it = c->egraphs.find(key);
+  if (it == c->egraphs.end()) {
+    if (c->egraphs.size() >= 64) {
+      for (auto& g : c->egraphs) (void)hipGraphExecDestroy(g.second);
+      c->egraphs.clear();
+    }
+    hipGraph_t g = nullptr;
+    NC_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int k = 0; k < np; ++k) {
+        StepArgs A = step_args(c, B, false);
+        A.z = c->zseg.p + size_t(k) * c->n_streams * size_t(c->V);
+        A.step_out = nullptr;
+        A.iv = c->iv.p;
+        A.ptok = c->ptok.p;
+        A.pos_base = c->posbase.p;
+        encode_step_pipelined(c, A, p0 + k, k, k == 0);
+      }
+      NC_HIP(hipStreamWaitEvent(c->st, c->ev_pred, 0));  // st2 joins the capture
+    } catch (...) {
+      hipGraph_t tmp = nullptr;
+      (void)hipStreamEndCapture(c->st, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      throw;
+    }
+    NC_HIP(hipStreamEndCapture(c->st, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    NC_HIP(e);
+    it = c->egraphs.emplace(key, ex).first;
+    c->stats.graph_captures += 1;
+  }
+  NC_HIP(hipGraphLaunch(it->second, c->st));
+  c->stats.graph_replays += 1;
+  // the chunk's last prediction, recorded inside the graph, is complete with it
+  NC_HIP(hipEventRecord(c->ev_pred, c->st));
 }
 
 void check_config(const nc_config* cfg) {
@@ -1376,6 +1448,14 @@ nc_status nc_encode_stream(nc_ctx* c, uint32_t ns, const int32_t* const* tokens,
       for (size_t i0 = 0; i0 < seg_len; i0 += pc) {
         const int np = int(std::min(size_t(pc), seg_len - i0));
         run_lm_head(c, c->yb.p, c->xinv.p, seg_ar + i0 * n, np * n, c->zseg.p);
+        bool uniform = true;
+        for (size_t i = i0; i < i0 + np; ++i) uniform = uniform && active[i] == active[i0];
+        const size_t p0 = a + i0;
+        if (pipe && uniform && p0 > 0 && p0 % 2 == 0 && np > 1 &&
+            !(c->cfg.features & NC_F_EAGER) && !profiling(c)) {
+          encode_chunk_graph(c, int(p0), np, active[i0]);
+          continue;
+        }
         for (size_t i = i0; i < i0 + np; ++i) {
           StepArgs A = step_args(c, active[i], false);
           A.z = c->zseg.p + (i - i0) * n * size_t(c->V);

@@ -102,8 +102,11 @@ struct StepArgs {
   float* dbg_pt;
   uint32_t* dbg_cdf;
   // Batched encode: every row is at position pos (>= 0), known to the host, and the update kernel
-  // takes the committed token from hist; -1: the position is S.ncommit[stream].
+  // takes the committed token from hist; -1: the position is S.ncommit[stream].  With pos_base
+  // (a device int; a step captured into a graph that is replayed for every chunk of positions)
+  // the position is pos + *pos_base.
   int pos;
+  const int* pos_base;
   // Updates run by the n-gram update kernel: kUpdCounts (token history, unigram and n-gram
   // counts, next contexts, ncommit) and / or kUpdMixer (mixer weights or ensemble gate, which
   // need the step's outcome).
@@ -122,7 +125,9 @@ void launch_vocab_step(const VocabParams& P, const StreamState& S, const StepArg
 // pos: the rows' position (>= 0, batched encode) or -1 (S.ncommit).
 void launch_ngram_predict(const VocabParams& P, const StreamState& S, const int32_t* rows, int B,
                           NgPart* parts, StepOut* step_out, const Outcome* out, hipStream_t s,
-                          int pos = -1);
+                          int pos = -1, const int* pos_base = nullptr);
+// *p = v (one thread): the position base of a replayed encode graph
+void launch_set_int(int* p, int v, hipStream_t s);
 // Only the step's distribution, interval and bias step (V1-V3, V4 for the ensemble), and only
 // the n-gram update kernel with the updates in A.upd.
 void launch_vocab_dist(const VocabParams& P, const StreamState& S, const StepArgs& A,

@@ -175,7 +175,7 @@ def test_many_streams_batch_and_alone_agree_bf16(weights):
     """24 BF16 streams coded together (prefill passes of thousands of attention items, one wave
     per item) and alone (a few hundred items per pass, a workgroup per quad plus the fold kernel)
     give the same bytes, and the batch decodes back exactly."""
-    ctx, _ = make_context(WL, precision="bf16", max_streams=24)
+    ctx, _ = make_context(WL, precision="bf16", max_streams=24, decode_graphs=True)
     streams = [synth.make_stream(150 + 7 * s, WL.shape.vocab, seed=300 + s, span=WL.span)
                for s in range(24)]
     together, _ = ctx.encode_stream(streams)

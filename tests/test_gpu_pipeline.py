@@ -178,9 +178,9 @@ def test_nc06_hybrid_round_trip(setup):
 
 
 def test_graph_replayed_passes_match_direct_launches(setup):
-    """Decode passes replayed from captured HIP graphs give the same tokens and the same probe
-    distributions as passes launched kernel by kernel; eager work and synchronisations run between
-    the replays, and every replay's output feeds the next decoded symbol."""
+    """Encode chunks and decode passes replayed from captured HIP graphs give the same bytes, the
+    same tokens and the same probe distributions as kernels launched one by one; eager work and
+    synchronisations run between the replays, and every replay's output feeds the next step."""
     _, w, toks, orc = setup
     import paper_2602_19626_amd as nc
     streams = [toks[:900], synth.make_stream(700, WL.shape.vocab, seed=21, span=WL.span),
@@ -188,7 +188,8 @@ def test_graph_replayed_passes_match_direct_launches(setup):
     ctxs = {}
     for graphs in (True, False):
         cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32",
-                             skip=WL.skip, mix_init=WL.mix_init, max_streams=3, graphs=graphs)
+                             skip=WL.skip, mix_init=WL.mix_init, max_streams=3, graphs=graphs,
+                             decode_graphs=graphs)
         ctxs[graphs] = nc.Context(cfg, synth.flat_weights(WL.shape, w))
     data_g, _ = ctxs[True].encode_stream(streams)
     data_e, _ = ctxs[False].encode_stream(streams)
