@@ -1070,8 +1070,12 @@ void encode_chunk_graph(nc_ctx* c, int p0, int np, int B) {
   }
   NC_HIP(hipGraphLaunch(it->second, c->st));
   c->stats.graph_replays += 1;
-  // the chunk's last prediction, recorded inside the graph, is complete with it
+  // Events recorded inside a capture order the graph's own nodes only; a later direct step waits
+  // on these (the chunk's last distribution and prediction), so they are recorded again after
+  // the whole replay.
   NC_HIP(hipEventRecord(c->ev_pred, c->st));
+  NC_HIP(hipEventRecord(c->ev_dist[0], c->st));
+  NC_HIP(hipEventRecord(c->ev_dist[1], c->st));
 }
 
 void check_config(const nc_config* cfg) {

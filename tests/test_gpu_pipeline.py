@@ -237,3 +237,28 @@ def test_edge_cases_empty_single_and_degenerate_streams(setup):
     assert ctx.stats()["skipped"] > 250              # the constant stream mostly skips
     with pytest.raises(nc.NacrithError):            # more streams than the context holds
         ctx.encode_stream(streams + [streams[1]])
+
+
+def test_encode_graph_chunks_then_direct_steps(setup):
+    """Uneven stream lengths make the batched encode alternate between replayed chunks (every
+    stream active through the chunk) and directly launched positions (a stream ends inside the
+    chunk): the bytes equal those of an eager context and of each stream coded alone."""
+    _, w, toks, orc = setup
+    import paper_2602_19626_amd as nc
+    lens = (1000, 1000, 700, 333, 90, 1000)
+    streams = [synth.make_stream(n, WL.shape.vocab, seed=40 + i, span=WL.span)
+               for i, n in enumerate(lens)]
+    out = {}
+    for graphs in (True, False):
+        cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, precision="fp32",
+                             skip=WL.skip, mix_init=WL.mix_init, max_streams=len(streams),
+                             graphs=graphs)
+        ctx = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+        out[graphs] = ctx.encode_stream(streams)[0]
+        st = ctx.stats()
+        assert (st["graph_replays"] > 10) == graphs
+        if graphs:
+            dec = ctx.decode_stream(out[graphs], list(lens))
+            assert all(np.array_equal(a, b) for a, b in zip(dec, streams))
+            assert ctx.encode_stream([streams[3]])[0][0] == out[graphs][3]
+    assert out[True] == out[False]
