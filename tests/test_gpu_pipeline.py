@@ -57,6 +57,9 @@ def test_encode_decode_roundtrip_and_gap(setup):
     assert np.array_equal(out[0], toks)
     gap = (bits[0] - orc.ideal_bits) / len(toks)
     assert gap < 0.01, gap
+    # the same bit count as the oracle coder on its own FP64 distributions
+    ref = op.encode(op.Settings.from_workload(WL), WL.shape, w, toks, block=1)
+    assert bits[0] == ref.n_bits, (bits[0], ref.n_bits)
     # re-encoding gives the same bytes (deterministic)
     data2, bits2 = ctx.encode_stream([toks])
     assert data2 == data and bits2 == bits
