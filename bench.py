@@ -177,7 +177,8 @@ def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024, 4096), reps: in
     """nc_quantize_cdf24 alone on float32 rows of softmax-shaped probabilities (up to 64 rows the
     segment reduce + scan kernels, more rows the one-workgroup-per-row kernel); algorithmic bytes
     per row = read 4V + write 4(V + 1).  From 1,024 rows at V = 49,152 the rows and their CDFs
-    (402 MB and more) exceed the 256 MB Infinity Cache."""
+    (402 MB and more) exceed the 256 MB Infinity Cache.  Beside it: a plain device-to-device copy
+    of the same rows (read 4V + write 4V), the streaming rate this part reaches in practice."""
     out = []
     g = torch.Generator(device="cuda").manual_seed(5)
     for rows in rows_list:
@@ -193,8 +194,22 @@ def cdf24_standalone(nc, torch, vocab: int, rows_list=(64, 1024, 4096), reps: in
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1000.0 / reps
         gbs = rows * (8 * vocab + 4) / (us * 1e-6) / 1e9
+        # the practical streaming ceiling for the same bytes: a device-to-device copy of the rows
+        q = torch.empty_like(p)
+        q.copy_(p)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            q.copy_(p)
+        e1.record()
+        torch.cuda.synchronize()
+        us_copy = e0.elapsed_time(e1) * 1000.0 / reps
+        gbs_copy = rows * 8 * vocab / (us_copy * 1e-6) / 1e9
         out.append({"rows": rows, "vocab": vocab, "us_per_call": round(us, 2),
-                    "achieved_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
+                    "achieved_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                    "copy_same_bytes_GBps": round(gbs_copy, 1),
+                    "frac_of_copy": round(gbs / gbs_copy, 4)})
+        del q
     return out
 
 
