@@ -81,20 +81,34 @@ def test_batch_invariance_of_coded_bytes(setup):
         assert np.array_equal(a, b)
 
 
-def test_ablation_switches_roundtrip(setup):
+ABLATION_RUNGS = [  # the paper's feature ladder (ablation table), plus two single switches
+    dict(cdf_total=1 << 16, use_head=False, use_ngram=False, use_skip=False, use_mixer=False),
+    dict(cdf_total=1 << 24, use_head=False, use_ngram=False, use_skip=False, use_mixer=False),
+    dict(cdf_total=1 << 24, use_head=True, use_ngram=False, use_skip=False, use_mixer=False),
+    dict(cdf_total=1 << 24, use_head=True, use_ngram=True, use_skip=True, use_mixer=False),
+    dict(cdf_total=1 << 24, use_head=True, use_ngram=True, use_skip=True, use_mixer=True),
+    dict(use_head=False),
+    dict(use_skip=False),
+]
+
+
+@pytest.mark.parametrize("over", ABLATION_RUNGS, ids=["A0", "A1", "A2", "A3", "A4", "nohead",
+                                                      "noskip"])
+def test_ablation_switches_roundtrip(setup, over):
+    """Each switch set round-trips exactly and codes within 0.01 bits/token of the oracle coder
+    on the oracle's own distributions with the same switches (the 2^16 CDF included).  Exact
+    equality is not implied: where an FP32 probability and the FP64 one straddle a quantisation
+    step, one count differs by one (the 2^16 rung codes 4,484 bits here against 4,483)."""
     ctx, w, toks, orc = setup
     import paper_2602_19626_amd as nc
     t = toks[:600]
-    for over in (dict(use_ngram=False, use_skip=False, use_mixer=False),
-                 dict(use_head=False), dict(use_mixer=False), dict(use_skip=False)):
-        cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, skip=WL.skip,
-                             mix_init=WL.mix_init, **over)
-        c = nc.Context(cfg, synth.flat_weights(WL.shape, w))
-        data, bits = c.encode_stream([t])
-        assert np.array_equal(c.decode_stream(data, [len(t)])[0], t), over
-        s = op.Settings.from_workload(WL, **over)
-        ref = op.encode(s, WL.shape, w, t, quantize=False, block=1)
-        assert (bits[0] - ref.ideal_bits) / len(t) < 0.02, over
+    cfg = nc.make_config(WL.shape, ngram_order=WL.ngram_order, skip=WL.skip,
+                         mix_init=WL.mix_init, warmup=WL.warmup, head_lr=WL.head_lr, **over)
+    c = nc.Context(cfg, synth.flat_weights(WL.shape, w))
+    data, bits = c.encode_stream([t])
+    assert np.array_equal(c.decode_stream(data, [len(t)])[0], t), over
+    ref = op.encode(op.Settings.from_workload(WL, **over), WL.shape, w, t, block=1)
+    assert abs(bits[0] - ref.n_bits) <= 0.01 * len(t), (over, bits[0], ref.n_bits)
 
 
 def test_error_paths(setup):
