@@ -644,6 +644,21 @@ GemmArgs args_lm(nc_ctx* c, const void* A, const float* Ainv, const int32_t* a_r
   return a;
 }
 
+// Rows from which a pass's normed GEMMs take their RMSNorm scales from one row_rms launch: with
+// many rows the tile kernels would otherwise each re-derive them from the block sums of squares
+// of their rows (once per column tile), before their first K part.  The scales are the same bits.
+constexpr int kRowScaleRows = 512;
+
+// The RMSNorm scale of each of the pass's n rows into c->xinv (from the block sums in c->xss).
+static void pass_row_scales(nc_ctx* c, int n) {
+  GemmArgs r{};
+  r.M = n;
+  r.K = c->d;
+  r.ssq = c->xss.p;
+  r.eps = c->cfg.norm_eps;
+  launch_row_rms(r, c->xinv.p, c->st);
+}
+
 // The kernels of one transformer pass (see run_pass).
 void pass_launches(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts o) {
   const int n = int(p.rows.size());
@@ -657,8 +672,12 @@ void pass_launches(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts
     Layer& L = c->layers[l];
     float* am = o.calib ? c->amax.p + 4 * l : nullptr;
     // QKV with RoPE and the KV-ring write
-    const GemmArgs a = args_qkv(c, l, n, drows, o.calib);
+    GemmArgs a = args_qkv(c, l, n, drows, o.calib);
     prof_begin(c, NC_K_QKV);
+    if (n >= kRowScaleRows) {
+      pass_row_scales(c, n);
+      a.inv = c->xinv.p;
+    }
     launch_gemm(prec, A_NORM, E_QKV, a, c->st, tile_for(c, o.calib, NC_G_QKV, n));
     prof_end(c, NC_K_QKV, gemm_bytes(a, A_NORM, E_QKV, prec, att), 2.0 * a.M * a.N * a.K);
     // attention
@@ -694,8 +713,12 @@ void pass_launches(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts
     launch_gemm(prec, A_DIRECT, E_RESID, ob, c->st, tile_for(c, o.calib, NC_G_OPROJ, n));
     prof_end(c, NC_K_OPROJ, gemm_bytes(ob, A_DIRECT, E_RESID, prec, att), 2.0 * n * ob.N * ob.K);
     // gate/up with SiLU
-    const GemmArgs gu = args_gateup(c, l, n, o.calib, am);
+    GemmArgs gu = args_gateup(c, l, n, o.calib, am);
     prof_begin(c, NC_K_GATEUP);
+    if (n >= kRowScaleRows) {
+      pass_row_scales(c, n);
+      gu.inv = c->xinv.p;
+    }
     launch_gemm(prec, A_NORM, E_GLU, gu, c->st, tile_for(c, o.calib, NC_G_GATEUP, n));
     prof_end(c, NC_K_GATEUP, gemm_bytes(gu, A_NORM, E_GLU, prec, att), 2.0 * n * gu.N * gu.K);
     // down projection + residual
@@ -706,15 +729,8 @@ void pass_launches(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts
   }
   const int nl = int(p.last.size() / 2);
   const int32_t* dl = reinterpret_cast<const int32_t*>(dstage + p.off_last);
-  {
-    // RMSNorm scale of every final row, for the output layer (same arithmetic as the GEMMs)
-    GemmArgs r{};
-    r.M = n;
-    r.K = c->d;
-    r.ssq = c->xss.p;
-    r.eps = c->cfg.norm_eps;
-    launch_row_rms(r, c->xinv.p, c->st);
-  }
+  // RMSNorm scale of every final row, for the output layer (same arithmetic as the GEMMs)
+  pass_row_scales(c, n);
   const int words = c->d * prec_bytes(prec) / 4;
   hipLaunchKernelGGL(copy_rows_kernel, dim3(nl), dim3(256), 0, c->st,
                      reinterpret_cast<const uint32_t*>(c->yb.p), c->xinv.p, dl, dl + nl, nl, words,
