@@ -1545,6 +1545,144 @@ __global__ __launch_bounds__(64 * FOLD_WAVES) void attention_fold_kernel(const A
 
 // x[r] = E[tok]; one wave per row, which also writes the row's inverse RMS (row_inv_rms order).
 // x[r] = E[tok], the block sums of squares of the row, and y[r] = quantise(x[r] * gain)
+// Few items, FP32 (decode): the quad kernel's work spread over four workgroups per quad, so that
+// each chunk's MFMA chains run on four SIMDs instead of one.  Workgroup (item, quad, chunk):
+// wave w runs the score chain of key block w, the four blocks' scores meet in LDS, every wave
+// takes the chunk's softmax (the same code, the same bits), and wave w runs the P*V chain of
+// head-dimension block w.  The chunk state is published at device scope: each store is written
+// through to the device's coherence point, every wave waits until its stores are acknowledged
+// (s_waitcnt 0), and after a barrier one thread counts the chunk in with a device-scope atomic.
+// The workgroup that brings the count to the quad's number of chunks reads the quad's chunk
+// states from that point, folds them in order (as the quad kernel does, hd block w in wave w),
+// stores the quad state for the fold kernel and resets the count to zero for the next launch.
+// No thread waits for another workgroup, so the launch always drains.
+constexpr int kChunkItems = 24;  // largest item count of the chunk-parallel path
+constexpr int CST = 6;           // floats per lane of one wave's chunk state: m, l, o[4]
+
+__device__ __forceinline__ float* chunk_slot(const AttnArgs& a, int item, int qi, int cw, int w) {
+  float* base = a.ws + (size_t)a.n_items * MAXQ * QSTATE * 64;  // after the quad states
+  return base + ((((size_t)item * MAXQ + qi) * QCH + cw) * 4 + w) * CST * 64;
+}
+
+__global__ __launch_bounds__(256) void attention_chunk_kernel(const AttnArgs a) {
+  __shared__ float s_st[4][4][64];  // scores [key block][element][lane]
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int cw = blockIdx.x % QCH, rest = blockIdx.x / QCH;
+  const int item = rest % a.n_items, qi = rest / a.n_items;
+  const AttnItem it = a.items[item];
+  int c_lo, c_hi;
+  item_chunks(a, it, c_lo, c_hi);
+  const int q0 = (c_lo / QCH + qi) * QCH, ch = q0 + cw;
+  if (ch < c_lo || ch > c_hi) return;  // not a chunk of the item (never counted)
+  const AttnCol c = attn_col(a, it, col);
+  const int hd = a.hd, nhb = hd / 16;
+  QFrag<P_F32> q;
+  load_q<P_F32>(q, a, c, grp);
+  const float* Kc = static_cast<const float*>(a.k_cache);
+  const float* Vt = static_cast<const float*>(a.vt_cache);
+  const long long sbase = (long long)it.stream * a.kv_stride + (long long)it.kvh * a.ring * hd;
+  const int key0 = ch * KCH;
+  const int base = key0 % a.ring;
+  auto slot_of = [&](int off) {
+    const int t = base + off;
+    return t >= a.ring ? t - a.ring : t;
+  };
+  const int vslot = slot_of(16 * grp);
+  // key block w's K fragment and head-dimension block w's V^T fragment (loads clamped into
+  // range and masked afterwards, as in chunk_partial)
+  v4f kf[4], vf[4];
+  {
+    const long long ks = sbase + (long long)slot_of(chunk_key(w, col)) * hd;
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      const int k = 16 * grp + 4 * qd;
+      const v4f v = *reinterpret_cast<const v4f*>(Kc + ks + min(k, hd - 4));
+      kf[qd] = k < hd ? v : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    const int hc = min(w, nhb - 1);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const v4f v = *reinterpret_cast<const v4f*>(Vt + sbase + (long long)(hc * 16 + col) * a.ring +
+                                                  vslot + 4 * b);
+      vf[b] = w < nhb ? v : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first MFMA
+  v4f sw = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < HDMAX / 4; ++s)
+    sw = __builtin_amdgcn_mfma_f32_16x16x4f32(kf[s >> 2][s & 3], q.f[s], sw, 0, 0, 0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) s_st[w][j][lane] = sw[j];
+  __syncthreads();
+  v4f st[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st[b][j] = s_st[b][j][lane];
+  ChunkState r;
+  state_empty(r);
+  chunk_softmax(st, a, c, key0, grp, r.m, r.l);
+  if (w < nhb) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        r.o[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[b][j], st[b][j], r.o[0], 0, 0, 0);
+  }
+  // publish this wave's part of the chunk state
+  {
+    float* dst = chunk_slot(a, item, qi, cw, w);
+    auto put = [&](int i, float v) {
+      __hip_atomic_store(dst + i * 64 + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    put(0, r.m);
+    put(1, r.l);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) put(2 + j, r.o[0][j]);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores are acknowledged
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nv = min(q0 + QCH - 1, c_hi) - max(q0, c_lo) + 1;  // the quad's chunks
+    const int old = __hip_atomic_fetch_add(a.ctr + item * MAXQ + qi, 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    s_last = old == nv - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(a.ctr + item * MAXQ + qi, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // the quad state: its chunks folded in order from the empty state (hd block w in wave w)
+  ChunkState qs, p;
+  state_empty(qs);
+  state_empty(p);
+  for (int k = 0; k < QCH; ++k) {
+    if (q0 + k < c_lo || q0 + k > c_hi) continue;
+    const float* src = chunk_slot(a, item, qi, k, w);
+    auto get = [&](int i) {
+      return __hip_atomic_load(src + i * 64 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    p.m = get(0);
+    p.l = get(1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) p.o[0][j] = get(2 + j);
+    fold(qs, p, 1);
+  }
+  // the fold kernel's layout (state_put): m, l, then o[hb][j] at 2 + 4 hb + j
+  float* qd = a.ws + ((long long)item * MAXQ + qi) * QSTATE * 64;
+  if (w == 0) {
+    qd[lane] = qs.m;
+    qd[64 + lane] = qs.l;
+  }
+  if (w < nhb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) qd[(2 + w * 4 + j) * 64 + lane] = qs.o[0][j];
+  }
+}
+
 template <int P>
 __global__ void embed_kernel(const float* __restrict__ E, const RowMeta* __restrict__ rows, int n,
                              int d, float* __restrict__ x, float* __restrict__ ssq, void* y,
@@ -1760,7 +1898,11 @@ template <int PA, int PO>
 static void attn_go(const AttnArgs& a, bool parallel, hipStream_t s) {
   if (parallel) {
     const int nq = attention_quads(a.ctx_len);
-    hipLaunchKernelGGL((attention_quad_kernel<PA>), dim3(a.n_items * nq), dim3(256), 0, s, a);
+    if (PA == P_F32 && a.ctr && a.n_items <= kChunkItems) {
+      hipLaunchKernelGGL(attention_chunk_kernel, dim3(a.n_items * nq * QCH), dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((attention_quad_kernel<PA>), dim3(a.n_items * nq), dim3(256), 0, s, a);
+    }
     hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64 * FOLD_WAVES), 0, s,
                        a);
   } else {
@@ -1770,8 +1912,12 @@ static void attn_go(const AttnArgs& a, bool parallel, hipStream_t s) {
 }
 
 size_t attention_ws_bytes(int n_items) {
-  return size_t(n_items) * MAXQ * QSTATE * 64 * sizeof(float);
+  const size_t quads = size_t(n_items) * MAXQ * QSTATE * 64;
+  const size_t chunks = n_items <= kChunkItems ? size_t(n_items) * MAXQ * QCH * 4 * CST * 64 : 0;
+  return (quads + chunks) * sizeof(float);
 }
+
+size_t attention_counters(int n_items) { return size_t(n_items) * MAXQ; }
 
 // parallel: a workgroup per (item, quad of chunks) and a fold kernel (few items, decode);
 // otherwise one wave per item (prefill).  Both produce the same bits.

@@ -84,6 +84,8 @@ struct AttnArgs {
   float* ws;            // group states of the parallel path
   size_t ws_bytes;
   int xcd_place;        // parallel path: items share a stream's K/V; place them XCD-aware
+  int* ctr;             // parallel path, optional: attention_counters(n_items) counters, zero
+                        // between launches (given: few FP32 items run one workgroup per chunk)
 };
 
 // Launch shape of one GEMM.  Every shape evaluates the same per-part MFMA chains and adds them in
@@ -110,6 +112,7 @@ void launch_row_rms(const GemmArgs& a, float* inv, hipStream_t s);
 void launch_attention(int prec_att, int prec_out, const AttnArgs& a, bool parallel,
                       hipStream_t s);
 size_t attention_ws_bytes(int n_items);
+size_t attention_counters(int n_items);
 // x[r] = E[rows[r].tok], its block sums of squares ssq[r][d/16] and the first normed GEMM's
 // operand y[r] = quantise(x[r] * gain) in precision prec (FP8: times inv_scale)
 void launch_embed(const float* E, const RowMeta* rows, int n, int d, float* x, float* ssq,

@@ -112,6 +112,7 @@ struct nc_ctx {
   DevBuf<int32_t> lastrow;  // per stream: row of its last position in the latest pass
   DevBuf<float> xinv;       // inverse RMS of each pass row's residual
   DevBuf<float> aws;        // attention group states (decode path)
+  DevBuf<int32_t> actr;     // attention chunk counters (zero between launches)
   DevBuf<float> xss;        // block sums of squares of each pass row's residual [rows][d/16]
   DevBuf<float> hinv;       // RMSNorm scale of each stream's newest row (its operand in hlast)
   DevBuf<float> yb;         // operand of the next normed GEMM, quantise(x * gain) [rows][d]
@@ -184,7 +185,8 @@ nc_ctx::~nc_ctx() {
                          &dbgp, &dbgpt};
   for (auto* q : fb) q->release();
   DevBuf<int32_t>* ib[] = {&uni, &nseen, &hist, &ncommit, &moded, &next_ctx, &keys, &kidx,
-                           &pool, &pool_n, &pool_sum, &nctx, &lastrow, &steprows, &arows};
+                           &pool, &pool_n, &pool_sum, &nctx, &lastrow, &steprows, &arows,
+                           &actr};
   for (auto* q : ib) q->release();
   kc.release();
   vc.release();
@@ -704,6 +706,7 @@ void pass_launches(nc_ctx* c, const PassPlan& p, const uint8_t* dstage, BodyOpts
     if (par) {
       t.ws = c->aws.p;
       t.ws_bytes = c->aws.n * 4;
+      t.ctr = c->actr.p;
     }
     launch_attention(att, prec, t, par, c->st);
     prof_end(c, NC_K_ATTN, p.attn_bytes, p.attn_flops);
@@ -1144,6 +1147,10 @@ nc_status nc_create(const nc_config* cfg, const float* w, nc_ctx** out) {
     NC_HIP(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
     for (hipEvent_t* e : {&c->ev_dist[0], &c->ev_dist[1], &c->ev_pred})
       NC_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    // the attention chunk counters start at zero; every launch leaves them at zero
+    c->actr.alloc(attention_counters(int(kAttnParallelItems)));
+    NC_HIP(hipMemsetAsync(c->actr.p, 0, c->actr.n * sizeof(int32_t), c->st));
+    NC_HIP(hipStreamSynchronize(c->st));
     c->prec = cfg->precision == NC_FP32 ? P_F32 : cfg->precision == NC_BF16 ? P_BF16 : P_FP8;
     c->att = c->prec == P_F32 ? P_F32 : P_BF16;
     c->d = cfg->d_model;
