@@ -39,7 +39,7 @@ KERNEL_NAME_RE = {"qkv": r"gemm_\w*kernel<\d+, \d+, 3\b", "gateup": r"gemm_\w*ke
                   "lmhead": r"gemm_\w*kernel<\d+, \d+, 0\b", "attn": r"attention_\w*kernel",
                   "vocab": r"(vocab_\w*|ensemble_bias)_kernel", "ngram": r"ngram_\w*_kernel"}
 # one dispatch per class launch matches these (a class launch may run several kernels)
-KERNEL_PRIMARY_RE = {"attn": r"attention_(quad|seq)_kernel", "vocab": r"vocab_lse_kernel",
+KERNEL_PRIMARY_RE = {"attn": r"attention_(quad|chunk|seq)_kernel", "vocab": r"vocab_lse_kernel",
                      "ngram": r"ngram_dense_kernel"}
 PROBE_RE = r"neg"   # the plain streaming probe kernel (torch.neg: reads N bytes, writes N bytes)
 
