@@ -1496,45 +1496,82 @@ __global__ __launch_bounds__(256) void attention_quad_kernel(const AttnArgs a) {
   state_put(a.ws + ((long long)item * MAXQ + qi) * QSTATE * 64, qs, lane);
 }
 
-// Few items, second kernel: quads -> groups -> output, one workgroup per item.  Wave w folds the
-// quads of the item's w-th group (their states loaded together) and leaves the group state in
-// LDS; wave 0 then folds the groups in order.  The folds are the sequential kernel's, in the same
-// order, so the output is the same.
+// Few items, second kernel: quads -> groups -> output, one workgroup per (item, head-dimension
+// block hb): a state's m and l and its block hb fold on their own (the other blocks only scale
+// alike), so the four blocks' folds run side by side.  Wave w folds the quads of the item's w-th
+// group (their states loaded together) and leaves the group state in LDS; wave 0 then folds the
+// groups in order.  The folds are the sequential kernel's, in the same order, so the output is
+// the same.
 constexpr int FOLD_WAVES = (MAXQ + GQ - 2) / GQ + 1;  // groups an item may span
+constexpr int BSTATE = 2 + 4;                         // floats per lane of a one-block state
 template <int PO>
 __global__ __launch_bounds__(64 * FOLD_WAVES) void attention_fold_kernel(const AttnArgs a) {
-  __shared__ float gst[FOLD_WAVES][QSTATE * 64];
+  __shared__ float gst[FOLD_WAVES][BSTATE * 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int item = blockIdx.x;
+  const int item = blockIdx.x, hb = blockIdx.y;
   const AttnItem it = a.items[item];
-  const int nhb = a.hd / 16;
   int c_lo, c_hi;
   item_chunks(a, it, c_lo, c_hi);
   const int qlo = c_lo / QCH, qhi = c_hi / QCH;
   const int gfirst = (qlo / GQ) * GQ;
   const int ng = (qhi - gfirst) / GQ + 1;  // <= FOLD_WAVES: qhi - qlo < MAXQ
   const float* src = a.ws + (long long)item * MAXQ * QSTATE * 64;
+  // m, l and block hb of a quad state (state_put layout) as a one-block state
+  auto get_block = [&](ChunkState& st, const float* q) {
+    st.m = q[lane];
+    st.l = q[64 + lane];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st.o[0][j] = q[(2 + hb * 4 + j) * 64 + lane];
+  };
   if (w < ng) {
     const int g0 = gfirst + w * GQ;
     ChunkState gs, p[GQ];
 #pragma unroll
     for (int u = 0; u < GQ; ++u)
-      if (g0 + u >= qlo && g0 + u <= qhi) state_get(p[u], src + (g0 + u - qlo) * QSTATE * 64, lane);
+      if (g0 + u >= qlo && g0 + u <= qhi) get_block(p[u], src + (g0 + u - qlo) * QSTATE * 64);
     state_empty(gs);
 #pragma unroll
     for (int u = 0; u < GQ; ++u)
-      if (g0 + u >= qlo && g0 + u <= qhi) fold(gs, p[u], nhb);
-    state_put(gst[w], gs, lane);
+      if (g0 + u >= qlo && g0 + u <= qhi) fold(gs, p[u], 1);
+    gst[w][lane] = gs.m;
+    gst[w][64 + lane] = gs.l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gst[w][(2 + j) * 64 + lane] = gs.o[0][j];
   }
   __syncthreads();
   if (w != 0) return;
   ChunkState run, gs;
   state_empty(run);
+  state_empty(gs);
   for (int k = 0; k < ng; ++k) {
-    state_get(gs, gst[k], lane);
-    fold(run, gs, nhb);
+    gs.m = gst[k][lane];
+    gs.l = gst[k][64 + lane];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gs.o[0][j] = gst[k][(2 + j) * 64 + lane];
+    fold(run, gs, 1);
   }
-  float omax = attn_store<PO>(a, it, run, col, grp);
+  // output block hb of the lane's column: attn_store's arithmetic for one block
+  float omax = 0.f;
+  if (col < it.ncols) {
+    const int g = a.Hq / a.Hk, hd = a.hd;
+    const int cc = it.c0 + col;
+    const long long orow = it.row_base + cc / g;
+    const int oh = it.kvh * g + cc % g;
+    const float oinv = (PO == P_FP8) ? 1.0f / a.out_scale : 1.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = hb * 16 + grp * 4 + j;
+      const float o = run.o[0][j] / run.l;
+      const long long idx = orow * ((long long)a.Hq * hd) + (long long)oh * hd + d;
+      omax = fmaxf(omax, fabsf(o));
+      if constexpr (PO == P_F32)
+        PT<P_F32>::store(a.out, idx, o, 1.f);
+      else if constexpr (PO == P_BF16)
+        PT<P_BF16>::store(a.out, idx, o, 1.f);
+      else
+        PT<P_FP8>::store(a.out, idx, o, oinv);
+    }
+  }
   if (a.out_amax) {
     omax = wave_max_f(omax);
     if (lane == 0) atomic_max_abs(a.out_amax, omax);
@@ -1903,8 +1940,8 @@ static void attn_go(const AttnArgs& a, bool parallel, hipStream_t s) {
     } else {
       hipLaunchKernelGGL((attention_quad_kernel<PA>), dim3(a.n_items * nq), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items), dim3(64 * FOLD_WAVES), 0, s,
-                       a);
+    hipLaunchKernelGGL((attention_fold_kernel<PO>), dim3(a.n_items, a.hd / 16),
+                       dim3(64 * FOLD_WAVES), 0, s, a);
   } else {
     hipLaunchKernelGGL((attention_seq_kernel<PA, PO>), dim3((a.n_items + 3) / 4), dim3(256), 0, s,
                        a);
